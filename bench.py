@@ -1,0 +1,239 @@
+"""Throughput of the rounded-KLT codec hot path on one MI355X.
+
+Workload (one step = one pass of the whole path over the batch): 256 uint8
+images of 1024 x 1024, seeded separable AR(1) fields; rho drawn uniformly
+from {0.1, 0.3, 0.5, 0.7, 0.9, 0.95}, alpha from {1, 2, 3}; image i keeps
+r = 1 + (i mod 64) zig-zag coefficients; N = 8, level shift 128.  alpha = 1
+gives T = round(K) = 0 at N = 8 (every |K_ij| < 1/2), which the library
+rejects as singular: those images are counted and left out of the batch.
+A step is one persistent launch of the batched plan (forward, zonal stage,
+inverse, reconstruction, per-image SSE/MSE/PSNR), inputs resident in HBM.
+
+Prints one JSON line.  The plain path (one launch per image) is timed on the
+same batch for comparison, the streaming copy kernel gives the measured
+bandwidth ceiling, and the oracle is timed on a bounded CPU sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+from concurrent.futures import ProcessPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2111_14239_amd.inputs import fixed_batch  # noqa: E402
+
+METRIC = "Mpixel/s fwd+zonal+inv+PSNR (batched vs plain), % HBM peak, p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PIXEL = 2  # read the uint8 pixel, write the uint8 reconstruction
+KERNEL = "rklt_block8_kernel"
+CPU_SAMPLE_IMAGES = 64
+
+
+def _gen(spec):
+    return spec.image()
+
+
+def _source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("codec.hip", "abi.cpp", "rklt_internal.h"):
+        with open(os.path.join(ROOT, "paper_2111_14239_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(pixels: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "block8_batch256_1024_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != _source_hash() or t.get("pixels") != pixels:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(specs) -> dict:
+    """Time the oracle on the first CPU_SAMPLE_IMAGES valid images in a child
+    process restricted to one thread."""
+    code = r"""
+import sys, time, json
+sys.path.insert(0, %r)
+from oracle import rklt_oracle as o
+from paper_2111_14239_amd.inputs import ImageSpec
+specs = json.loads(sys.argv[1])
+imgs = [ImageSpec(**s).image() for s in specs]
+t0 = time.perf_counter()
+px = 0
+for s, img in zip(specs, imgs):
+    o.codec(img, s["N"], s["rho"], s["alpha"], s["r"], s["ell"])
+    px += img.size
+dt = time.perf_counter() - t0
+print(json.dumps({"seconds": dt, "pixels": px}))
+""" % ROOT
+    sample = [dict(H=s.H, W=s.W, rho=s.rho, alpha=s.alpha, r=s.r, seed=s.seed, N=s.N, ell=s.ell)
+              for s in specs[:CPU_SAMPLE_IMAGES]]
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code, json.dumps(sample)], capture_output=True, text=True,
+                         env=env, check=True).stdout
+    r = json.loads(out.strip().splitlines()[-1])
+    return {"value": r["pixels"] / r["seconds"] / 1e6, "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} of the batch's images (1024x1024, exact-rational reconstruction), "
+                      f"{r['seconds']:.1f} s on one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--images", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--wg", type=int, default=0)
+    ap.add_argument("--bpt", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the codec shards by whole images with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2111_14239_amd import rklt
+
+    specs_all = fixed_batch(args.images, 1024)
+    ctx = rklt.Context(0)
+    specs, tids, rejected = [], [], 0
+    for s in specs_all:
+        try:
+            tids.append(ctx.transform_id(8, s.rho, s.alpha))
+            specs.append(s)
+        except rklt.RkltError as e:
+            if e.status != rklt.E_SINGULAR:
+                raise
+            rejected += 1
+    with ProcessPoolExecutor(max_workers=8) as ex:
+        imgs = list(ex.map(_gen, specs, chunksize=4))
+    n = len(specs)
+    H = W = 1024
+    src = torch.from_numpy(np.stack(imgs)).to("cuda")
+    dst = torch.empty_like(src)
+    del imgs
+    descs = [rklt.image_desc(src[i], tids[i], specs[i].r, dst=dst[i]) for i in range(n)]
+    tuning = rklt.make_tuning(args.wg, args.bpt, args.grid)
+    plan = ctx.plan(descs, tuning)
+    res = rklt.new_results(n)
+    pixels = n * H * W
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.run(int(res.data_ptr()), stream)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record(stream)
+    for k in range(args.steps):
+        starts[k].record(stream)
+        plan.run(int(res.data_ptr()), stream)
+        ends[k].record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_all0.elapsed_time(t_all1)
+    per_launch = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    ms_per_step = ms_total / args.steps
+    avg_launch_ms = float(per_launch.mean())
+    results = rklt.read_results(res)
+    assert all(r["tiles"] > 0 for r in results)
+
+    # plain path: one launch per image
+    res_plain = rklt.new_results(n)
+    for i in range(n):
+        ctx.codec(descs[i], int(res_plain.data_ptr()) + i * rklt.RESULT_BYTES, tuning, stream)
+    torch.cuda.synchronize()
+    p0 = torch.cuda.Event(enable_timing=True)
+    p1 = torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for _ in range(args.plain_steps):
+        for i in range(n):
+            ctx.codec(descs[i], int(res_plain.data_ptr()) + i * rklt.RESULT_BYTES, tuning, stream)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = p0.elapsed_time(p1) / args.plain_steps
+    plain = rklt.read_results(res_plain)
+    assert [r["sse"] for r in plain] == [r["sse"] for r in results], "plain and batched paths disagree"
+
+    # measured streaming-copy ceiling (same bytes: read the batch, write a copy)
+    nbytes = src.numel()
+    for _ in range(3):
+        rklt.copy_bytes(src, dst, nbytes, stream)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(20):
+        rklt.copy_bytes(src, dst, nbytes, stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes / (c0.elapsed_time(c1) / 20 / 1e3) / 1e9
+    # restore the reconstructions overwritten by the copy
+    plan.run(int(res.data_ptr()), stream)
+    torch.cuda.synchronize()
+
+    achieved = BYTES_PER_PIXEL * pixels / (avg_launch_ms / 1e3) / 1e9
+    traffic = _traffic(pixels)
+    line = {
+        "metric": METRIC,
+        "value": pixels / (ms_per_step / 1e3) / 1e6,
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8 in/out, i32 forward, f32 inverse",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch of 1024x1024 uint8 AR(1) images, rho in {0.1,0.3,0.5,0.7,0.9,0.95}, "
+                        "alpha in {1,2,3} (alpha=1 rejected as singular), r = 1 + (i mod 64), N=8, "
+                        "level shift 128, one persistent launch per step",
+            "images": n, "rejected_alpha1": rejected, "pixels": pixels,
+            "tiles": plan.tiles, "grid_wgs": plan.grid,
+            "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 2,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL,
+            "avg_launch_ms": avg_launch_ms,
+        },
+        "latency_ms": {"p50": float(np.percentile(per_launch, 50)),
+                       "p99": float(np.percentile(per_launch, 99))},
+        "plain": {"ms_per_step": plain_ms, "value": pixels / (plain_ms / 1e3) / 1e6,
+                  "launches_per_step": n},
+        "copy_ceiling_GBps": copy_gbs,
+        "mean_psnr_db": float(np.mean([r["psnr_db"] for r in results if np.isfinite(r["psnr_db"])])),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(specs)
+    plan.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

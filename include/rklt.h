@@ -1,0 +1,191 @@
+/*
+ * rklt.h -- C ABI of the MI355X (gfx950) rounded-KLT block codec.
+ *
+ * The operation is the JPEG-like compression experiment of Radünz, Bayer and
+ * Cintra, "Low-complexity Rounded KLT Approximation for Image Compression"
+ * (arXiv 2111.14239):
+ *
+ *   transform design  (§2.1, §2.2 Eq. 1, §2.3 Eq. 2)
+ *     K   the exact KLT of a first-order Markov signal with correlation rho
+ *     T   = round(alpha K), round(x) = floor(x + 1/2), element-wise
+ *     S   = diag(s), s_i = (T T^T)_ii^(-1/2);  T_hat = S T
+ *   codec             (§4.1, Appendix A)
+ *     every disjoint N x N sub-block A of an 8-bit image, shifted by ell:
+ *       B      = T (A - ell) T^T                  exact integer forward transform
+ *       B_hat  = (s s^T) (.) B                    scaling S folded into the zonal stage
+ *       keep the first r coefficients of the zig-zag scan, zero the rest
+ *       A'     = T_hat^-1 (masked B_hat) T_hat^-T + ell
+ *       recon  = clip(floor(A' + 1/2), 0, 255)
+ *     per image: SSE = sum (img - recon)^2, MSE = SSE / (H W),
+ *                PSNR = 10 log10(255^2 / MSE)  (+inf when MSE = 0)
+ *
+ * Conventions.  All matrices are row-major.  Row k of K and T is the k-th
+ * basis vector.  i (row of B) is the vertical frequency; the zig-zag scan is
+ * (0,0), (0,1), (1,0), (2,0), (1,1), (0,2), ...  Integer stages are exact
+ * (int32 on the device); scaling, inverse and PSNR run in FP32 on the device;
+ * the transform design runs in FP64 on the host.
+ *
+ * Errors.  Every call returns an rklt_status and never throws.  Argument
+ * errors are detected on the host before anything is launched;
+ * rklt_last_error() returns a thread-local message describing the most recent
+ * failure on the calling thread.
+ *
+ * Streams.  `stream` arguments are hipStream_t handles passed as void*;
+ * NULL is the default stream.  Device calls are asynchronous on that stream;
+ * their outputs are valid once the stream has been synchronised.
+ */
+#ifndef RKLT_H
+#define RKLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RKLT_OK = 0,
+  RKLT_E_INVAL = 1,    /* an argument is out of range or a pointer is NULL        */
+  RKLT_E_SINGULAR = 2, /* the rounded transform has a zero row or det T = 0       */
+  RKLT_E_RANGE = 3,    /* the exact integer stages would overflow int32           */
+  RKLT_E_NOMEM = 4,    /* a host or device allocation failed                      */
+  RKLT_E_HIP = 5,      /* a HIP runtime call or kernel launch failed              */
+  RKLT_E_STATE = 6     /* the call does not fit the object's state                */
+} rklt_status;
+
+#define RKLT_MAX_N 32
+
+/* flags of rklt_transform */
+#define RKLT_ORTHOGONAL 1u /* T T^T is diagonal, so T_hat^-1 = T_hat^T     */
+#define RKLT_ADDS_ONLY 2u  /* every entry of T lies in {0, +1, -1}        */
+
+/* One rounded KLT and everything the codec derives from it (host memory). */
+typedef struct {
+  int32_t N;                           /* block length, 2 <= N <= 32            */
+  int32_t flags;                       /* RKLT_ORTHOGONAL | RKLT_ADDS_ONLY      */
+  double rho;                          /* correlation coefficient, 0 < rho < 1  */
+  double alpha;                        /* expansion factor, alpha > 0           */
+  double K[RKLT_MAX_N * RKLT_MAX_N];   /* exact KLT (§2.1), first N*N used      */
+  int32_t T[RKLT_MAX_N * RKLT_MAX_N];  /* round(alpha K) (Eq. 2)                */
+  int64_t d[RKLT_MAX_N];               /* d_i = (T T^T)_ii                      */
+  double s[RKLT_MAX_N];                /* s_i = d_i^(-1/2), S = diag(s) (Eq. 1) */
+  double G[RKLT_MAX_N * RKLT_MAX_N];   /* T_hat^-1 = (S T)^-1                   */
+  int32_t max_abs;                     /* max |T_ij|                            */
+  int32_t max_row_l1;                  /* max_i sum_j |T_ij|                    */
+} rklt_transform;
+
+/* One image handed to the codec.  Pointers are device pointers. */
+typedef struct {
+  const uint8_t* src;   /* H rows of W pixels, row stride pitch_src bytes        */
+  uint8_t* dst;         /* reconstruction (same geometry), or NULL: PSNR only    */
+  int32_t* coef_out;    /* optional, verification: int32 B, H*W values          */
+  float* scaled_out;    /* optional, verification: float B_hat, H*W values      */
+  int32_t H, W;         /* multiples of N, 1 <= H, W                             */
+  int32_t pitch_src;    /* >= W, multiple of 8 bytes                             */
+  int32_t pitch_dst;    /* >= W, multiple of 8 bytes (ignored when dst is NULL)  */
+  int32_t transform_id; /* from rklt_ctx_add_transform                           */
+  int32_t r;            /* zig-zag coefficients kept per block, 1 <= r <= N*N    */
+  int32_t level_shift;  /* ell, 0 <= ell <= 255 (128 shifts to signed range)     */
+  int32_t reserved;     /* must be 0                                             */
+} rklt_image;
+/* coef_out / scaled_out layout: block-major; block (by, bx) of the image
+ * occupies N*N consecutive values starting at (by * (W/N) + bx) * N*N, in
+ * row-major (i, j) order.  Both hold every coefficient (not only the kept
+ * ones); scaled_out is (s s^T) (.) B before zonal masking.  Writing them adds
+ * 4 bytes per pixel each, so they are meant for verification only. */
+
+/* Per-image result (device memory, written by the codec).  acc and done are
+ * the codec's own accumulators: the array must be zero-filled once before its
+ * first use, and every completed call leaves them at zero again, so the same
+ * array can be reused without clearing it. */
+typedef struct {
+  uint64_t sse;    /* sum of squared pixel errors (exact)                       */
+  float mse;       /* sse / (H W) in FP32                                       */
+  float psnr_db;   /* 10 log10(255^2 / mse) in FP32, +inf when sse == 0         */
+  uint64_t acc;    /* internal: running SSE while the call is in flight         */
+  uint32_t done;   /* internal: finished tiles while the call is in flight      */
+  uint32_t tiles;  /* number of tiles the image was coded in (set when final)   */
+} rklt_result;
+
+/* Launch shape of the block kernels.  Zero fields take the defaults. */
+typedef struct {
+  int32_t wg_threads;        /* threads per workgroup: 64, 128 or 256            */
+  int32_t blocks_per_thread; /* N = 8 path: N x N blocks per thread per tile     */
+  int32_t grid_wgs;          /* persistent grid size in workgroups (0: auto)     */
+  int32_t reserved;
+} rklt_tuning;
+
+typedef struct rklt_ctx rklt_ctx;
+typedef struct rklt_plan rklt_plan;
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* rklt_last_error(void);
+
+/* ---- host-side transform design (no GPU needed) ------------------------- */
+
+/* Build T = round(alpha K_rho) for block length N and everything derived
+ * from it: the omega roots of §2.1 (one in each (k pi/N, (k+1) pi/N)), the
+ * eigenvalues lambda_k, K, T (Eq. 2), d, s and S (Eq. 1), and G = T_hat^-1.
+ * `out` is caller-owned.  Errors: E_INVAL (N outside 2..32, rho outside
+ * (0,1), alpha not positive and finite, out NULL); E_SINGULAR (a zero row of
+ * T or a singular T, e.g. alpha = 1 at N = 8, where every |K_ij| < 1/2). */
+rklt_status rklt_build_transform(int32_t N, double rho, double alpha, rklt_transform* out);
+
+/* The zig-zag scan of §4.1 for an N x N block: order[k] = i*N + j of the
+ * k-th scanned coefficient, k = 0 .. N*N-1.  `order` holds N*N int32 values
+ * (caller-owned).  Errors: E_INVAL (N outside 1..32, order NULL). */
+rklt_status rklt_zigzag(int32_t N, int32_t* order);
+
+/* ---- device context ----------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  The context owns a device-side
+ * table of up to 256 transforms; it allocates nothing else. */
+rklt_status rklt_ctx_create(int32_t device, rklt_ctx** out);
+rklt_status rklt_ctx_destroy(rklt_ctx* ctx);
+
+/* Upload a transform built by rklt_build_transform (N must be 4, 8, 16 or
+ * 32) into the context's table and return its id.  A transform whose T
+ * equals one already uploaded returns the existing id.  The copy is
+ * synchronous; it never touches entries that launched kernels may read.
+ * Errors: E_INVAL, E_RANGE (255 * max_row_l1^2 >= 2^31), E_NOMEM (table
+ * full), E_HIP. */
+rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32_t* id_out);
+
+/* ---- codec -------------------------------------------------------------- */
+
+/* Plain path: code one image with one kernel launch on `stream` (§4.1).
+ * `d_res` is one device rklt_result (see its zero-fill rule).  Errors:
+ * E_INVAL (geometry, r, ell, pointers, unknown transform id), E_HIP. */
+rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
+                       const rklt_tuning* tuning, void* stream);
+
+/* Batched path: a plan holds the work list of `n` images (host array of
+ * descriptors with device pointers) on the device: per image its tile range
+ * and parameters, and a tile -> image table, so that rklt_plan_run codes the
+ * whole batch in one persistent launch.  All images of a plan share N.
+ * Creating a plan validates every image (the first bad one is named in
+ * rklt_last_error), allocates and uploads the work list synchronously.
+ * `tuning` NULL takes the defaults.  A plan must not run concurrently with
+ * itself; different plans may run on different streams. */
+rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n,
+                             const rklt_tuning* tuning, rklt_plan** out);
+/* d_res: n device rklt_result, in the order of the plan's images. */
+rklt_status rklt_plan_run(rklt_plan* plan, rklt_result* d_res, void* stream);
+rklt_status rklt_plan_destroy(rklt_plan* plan);
+/* Number of tiles and of workgroups the plan launches (for reporting). */
+rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_wgs,
+                           int64_t* pixels);
+
+/* ---- measurement -------------------------------------------------------- */
+
+/* Copy nbytes from src to dst (device pointers, 16-byte aligned, nbytes a
+ * multiple of 16) with a plain streaming kernel: the bandwidth reference the
+ * codec's HBM traffic is compared with.  Errors: E_INVAL, E_HIP. */
+rklt_status rklt_copy_bytes(const void* src, void* dst, size_t nbytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RKLT_H */

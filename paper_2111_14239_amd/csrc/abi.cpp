@@ -1,0 +1,442 @@
+// C ABI of librklt: error slot, contexts (device transform table), image
+// validation, plans (device work lists) and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "rklt.h"
+#include "rklt_internal.h"
+
+struct rklt_ctx {
+  int device = 0;
+  int cus = 0;
+  rklt::DevTransform* d_table = nullptr;
+  std::vector<rklt::DevTransform> host;  // host mirror of the uploaded entries
+  std::mutex mu;
+};
+
+struct rklt_plan {
+  rklt_ctx* ctx = nullptr;
+  int N = 0;
+  bool block8 = false;
+  bool dump = false;
+  int n = 0;
+  rklt::DevImage* d_imgs = nullptr;
+  int32_t* d_tile_img = nullptr;
+  int64_t total_tiles = 0;
+  int blocks_per_tile = 0;
+  int blocks_per_thread = 1;
+  int wg = 256;
+  int grid = 0;
+  int64_t pixels = 0;
+};
+
+namespace rklt {
+
+namespace {
+thread_local char g_error[512] = "";
+
+constexpr int kDefaultWg = 256;
+constexpr int kDefaultBpt = 2;
+
+bool block8_fits(const DevTransform& t, int ell) {
+  // level shift 128 (pixel xor 0x80), int8 entries for the row dots and
+  // |Y| <= 128 * L1 within int16 for the column dots
+  return ell == 128 && t.N == 8 && t.max_abs <= 127 && 128 * t.max_row_l1 <= 32767;
+}
+
+hipError_t use_device(int device) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  return cur == device ? hipSuccess : hipSetDevice(device);
+}
+
+rklt_status hip_fail(const char* what, hipError_t e) {
+  return fail(RKLT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Check one image against the context and fill its device descriptor
+// (tile fields excluded).
+rklt_status check_image(rklt_ctx* ctx, const rklt_image& im, int index, DevImage* out, int* N_out) {
+  if (im.transform_id < 0 || im.transform_id >= static_cast<int>(ctx->host.size()))
+    return fail(RKLT_E_INVAL, "image %d: unknown transform_id %d", index, im.transform_id);
+  const DevTransform& t = ctx->host[im.transform_id];
+  const int N = t.N;
+  if (!im.src) return fail(RKLT_E_INVAL, "image %d: src is NULL", index);
+  if (im.H < N || im.W < N || im.H % N || im.W % N)
+    return fail(RKLT_E_INVAL, "image %d: H=%d W=%d are not positive multiples of N=%d", index, im.H, im.W, N);
+  if (static_cast<int64_t>(im.H) * im.W >= (int64_t{1} << 31))
+    return fail(RKLT_E_INVAL, "image %d: H*W=%lld exceeds 2^31-1 pixels", index,
+                static_cast<long long>(im.H) * im.W);
+  if (im.pitch_src < im.W || im.pitch_src % 8)
+    return fail(RKLT_E_INVAL, "image %d: pitch_src=%d must be >= W=%d and a multiple of 8", index,
+                im.pitch_src, im.W);
+  if (reinterpret_cast<uintptr_t>(im.src) % 8)
+    return fail(RKLT_E_INVAL, "image %d: src is not 8-byte aligned", index);
+  if (im.dst) {
+    if (im.pitch_dst < im.W || im.pitch_dst % 8)
+      return fail(RKLT_E_INVAL, "image %d: pitch_dst=%d must be >= W=%d and a multiple of 8", index,
+                  im.pitch_dst, im.W);
+    if (reinterpret_cast<uintptr_t>(im.dst) % 8)
+      return fail(RKLT_E_INVAL, "image %d: dst is not 8-byte aligned", index);
+  }
+  if (im.r < 1 || im.r > N * N)
+    return fail(RKLT_E_INVAL, "image %d: r=%d outside 1..%d", index, im.r, N * N);
+  if (im.level_shift < 0 || im.level_shift > 255)
+    return fail(RKLT_E_INVAL, "image %d: level_shift=%d outside 0..255", index, im.level_shift);
+  if (im.reserved != 0) return fail(RKLT_E_INVAL, "image %d: reserved field is not 0", index);
+  DevImage& d = *out;
+  std::memset(&d, 0, sizeof(d));
+  d.src = im.src;
+  d.dst = im.dst;
+  d.coef = im.coef_out;
+  d.scaled = im.scaled_out;
+  d.H = im.H;
+  d.W = im.W;
+  d.ps = im.pitch_src;
+  d.pd = im.dst ? im.pitch_dst : 0;
+  d.tid = im.transform_id;
+  d.r = im.r;
+  d.ell = im.level_shift;
+  d.D = diagonals_for(N, im.r);
+  d.bw = im.W / N;
+  d.nblocks = (im.H / N) * (im.W / N);
+  *N_out = N;
+  return RKLT_OK;
+}
+
+rklt_status check_tuning(const rklt_tuning* tu, int* wg, int* bpt, int* grid) {
+  *wg = kDefaultWg;
+  *bpt = kDefaultBpt;
+  *grid = 0;
+  if (!tu) return RKLT_OK;
+  if (tu->wg_threads) {
+    if (tu->wg_threads != 64 && tu->wg_threads != 128 && tu->wg_threads != 256)
+      return fail(RKLT_E_INVAL, "tuning: wg_threads=%d not in {64, 128, 256}", tu->wg_threads);
+    *wg = tu->wg_threads;
+  }
+  if (tu->blocks_per_thread) {
+    if (tu->blocks_per_thread < 1 || tu->blocks_per_thread > 16)
+      return fail(RKLT_E_INVAL, "tuning: blocks_per_thread=%d outside 1..16", tu->blocks_per_thread);
+    *bpt = tu->blocks_per_thread;
+  }
+  if (tu->grid_wgs < 0) return fail(RKLT_E_INVAL, "tuning: grid_wgs=%d is negative", tu->grid_wgs);
+  *grid = tu->grid_wgs;
+  if (tu->reserved != 0) return fail(RKLT_E_INVAL, "tuning: reserved field is not 0");
+  return RKLT_OK;
+}
+
+}  // namespace
+
+rklt_status fail(rklt_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(g_error, sizeof(g_error), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_error[0] = '\0'; }
+
+}  // namespace rklt
+
+using namespace rklt;
+
+extern "C" {
+
+const char* rklt_last_error(void) { return g_error; }
+
+rklt_status rklt_build_transform(int32_t N, double rho, double alpha, rklt_transform* out) {
+  clear_error();
+  return build_transform(N, rho, alpha, out);
+}
+
+rklt_status rklt_zigzag(int32_t N, int32_t* order) {
+  clear_error();
+  return zigzag(N, order);
+}
+
+rklt_status rklt_ctx_create(int32_t device, rklt_ctx** out) {
+  clear_error();
+  if (!out) return fail(RKLT_E_INVAL, "rklt_ctx_create: out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail("hipGetDeviceCount", e);
+  if (device < 0 || device >= count)
+    return fail(RKLT_E_INVAL, "rklt_ctx_create: device %d not in 0..%d", device, count - 1);
+  rklt_ctx* ctx = new (std::nothrow) rklt_ctx;
+  if (!ctx) return fail(RKLT_E_NOMEM, "rklt_ctx_create: out of host memory");
+  ctx->device = device;
+  if ((e = use_device(device)) != hipSuccess) {
+    delete ctx;
+    return hip_fail("hipSetDevice", e);
+  }
+  e = hipDeviceGetAttribute(&ctx->cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return hip_fail("hipDeviceGetAttribute", e);
+  }
+  e = hipMalloc(&ctx->d_table, sizeof(DevTransform) * kMaxTransforms);
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(RKLT_E_NOMEM, "rklt_ctx_create: hipMalloc of the transform table: %s", hipGetErrorString(e));
+  }
+  ctx->host.reserve(kMaxTransforms);
+  *out = ctx;
+  return RKLT_OK;
+}
+
+rklt_status rklt_ctx_destroy(rklt_ctx* ctx) {
+  clear_error();
+  if (!ctx) return fail(RKLT_E_INVAL, "rklt_ctx_destroy: ctx is NULL");
+  if (ctx->d_table) {
+    (void)use_device(ctx->device);
+    (void)hipFree(ctx->d_table);
+  }
+  delete ctx;
+  return RKLT_OK;
+}
+
+rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32_t* id_out) {
+  clear_error();
+  if (!ctx || !t || !id_out) return fail(RKLT_E_INVAL, "rklt_ctx_add_transform: NULL argument");
+  const int N = t->N;
+  if (N != 4 && N != 8 && N != 16 && N != 32)
+    return fail(RKLT_E_INVAL, "rklt_ctx_add_transform: N=%d; the codec supports N in {4, 8, 16, 32}", N);
+  int max_abs = 0, max_l1 = 0;
+  for (int i = 0; i < N; ++i) {
+    int l1 = 0;
+    for (int j = 0; j < N; ++j) {
+      const int v = std::abs(t->T[i * N + j]);
+      if (v > 1000000) return fail(RKLT_E_RANGE, "rklt_ctx_add_transform: |T| too large");
+      l1 += v;
+      max_abs = v > max_abs ? v : max_abs;
+    }
+    if (t->d[i] <= 0 || !(t->s[i] > 0.0))
+      return fail(RKLT_E_SINGULAR, "rklt_ctx_add_transform: row %d has d_i <= 0", i);
+    max_l1 = l1 > max_l1 ? l1 : max_l1;
+  }
+  // |B| <= 255 * L1^2 for pixels shifted by any ell in 0..255
+  if (255.0 * max_l1 * max_l1 >= 2147483647.0)
+    return fail(RKLT_E_RANGE, "rklt_ctx_add_transform: 255 * L1^2 = %.0f overflows int32 (L1=%d)",
+                255.0 * max_l1 * max_l1, max_l1);
+
+  DevTransform dt;
+  std::memset(&dt, 0, sizeof(dt));
+  dt.N = N;
+  dt.flags = t->flags;
+  dt.max_abs = max_abs;
+  dt.max_row_l1 = max_l1;
+  int32_t order[RKLT_MAX_N * RKLT_MAX_N];
+  zigzag(N, order);
+  for (int k = 0; k < N * N; ++k) dt.rank[order[k]] = k;
+  for (int i = 0; i < N; ++i) {
+    int sig = 0;
+    for (int j = 0; j < N; ++j) {
+      sig += t->T[i * N + j];
+      dt.T[i * N + j] = t->T[i * N + j];
+      dt.w[i * N + j] = static_cast<float>(t->s[i] * t->s[j]);
+      dt.G[i * N + j] = static_cast<float>(t->G[i * N + j]);
+      dt.Ti[i * N + j] = static_cast<float>(t->G[i * N + j] * t->s[j]);
+    }
+    dt.sig[i] = sig;
+  }
+  if (N == 8 && max_abs <= 127) {
+    for (int j = 0; j < 8; ++j) {
+      for (int h = 0; h < 2; ++h) {
+        uint32_t word = 0;
+        for (int b = 0; b < 4; ++b) word |= (static_cast<uint32_t>(t->T[j * 8 + 4 * h + b]) & 0xffu) << (8 * b);
+        dt.t8[j][h] = static_cast<int32_t>(word);
+      }
+      for (int p = 0; p < 4; ++p) {
+        const uint32_t lo = static_cast<uint32_t>(t->T[j * 8 + 2 * p]) & 0xffffu;
+        const uint32_t hi = static_cast<uint32_t>(t->T[j * 8 + 2 * p + 1]) & 0xffffu;
+        dt.t16[j][p] = static_cast<int32_t>(lo | (hi << 16));
+      }
+    }
+  }
+
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  for (size_t k = 0; k < ctx->host.size(); ++k) {
+    const DevTransform& o = ctx->host[k];
+    if (o.N == N && std::memcmp(o.T, dt.T, sizeof(int32_t) * N * N) == 0) {
+      *id_out = static_cast<int32_t>(k);
+      return RKLT_OK;
+    }
+  }
+  if (ctx->host.size() >= static_cast<size_t>(kMaxTransforms))
+    return fail(RKLT_E_NOMEM, "rklt_ctx_add_transform: table full (%d transforms)", kMaxTransforms);
+  const int id = static_cast<int>(ctx->host.size());
+  hipError_t e = use_device(ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  e = hipMemcpy(ctx->d_table + id, &dt, sizeof(dt), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail("rklt_ctx_add_transform: hipMemcpy", e);
+  ctx->host.push_back(dt);
+  *id_out = id;
+  return RKLT_OK;
+}
+
+rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res, const rklt_tuning* tuning,
+                       void* stream) {
+  clear_error();
+  if (!ctx || !img || !d_res) return fail(RKLT_E_INVAL, "rklt_codec: NULL argument");
+  int wg, bpt, grid_req;
+  rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
+  if (st) return st;
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  int N = 0;
+  {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if ((st = check_image(ctx, *img, 0, &a.one, &N))) return st;
+    a.dump = (img->coef_out || img->scaled_out) ? 1 : 0;
+    const bool b8 = block8_fits(ctx->host[img->transform_id], img->level_shift);
+    a.blocks_per_thread = b8 ? bpt : 1;
+    a.blocks_per_tile = b8 ? wg * bpt : generic_blocks_per_tile(N);
+    a.one.tile0 = 0;
+    a.one.ntiles = (a.one.nblocks + a.blocks_per_tile - 1) / a.blocks_per_tile;
+    a.total_tiles = a.one.ntiles;
+    a.tf = ctx->d_table;
+    a.res = d_res;
+    hipError_t e = use_device(ctx->device);
+    if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+    const int grid = a.total_tiles;
+    return b8 ? launch_block8(a, grid, wg, stream) : launch_generic(N, a, grid, stream);
+  }
+}
+
+rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, const rklt_tuning* tuning,
+                             rklt_plan** out) {
+  clear_error();
+  if (!ctx || !imgs || !out || n < 1) return fail(RKLT_E_INVAL, "rklt_plan_create: NULL argument or n < 1");
+  *out = nullptr;
+  int wg, bpt, grid_req;
+  rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
+  if (st) return st;
+  std::vector<DevImage> dimgs(static_cast<size_t>(n));
+  int N = 0;
+  bool b8 = true, dump = false;
+  {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    for (int k = 0; k < n; ++k) {
+      int Nk = 0;
+      if ((st = check_image(ctx, imgs[k], k, &dimgs[k], &Nk))) return st;
+      if (k == 0) N = Nk;
+      else if (Nk != N)
+        return fail(RKLT_E_INVAL, "image %d: N=%d differs from N=%d of image 0 (one N per plan)", k, Nk, N);
+      b8 = b8 && block8_fits(ctx->host[imgs[k].transform_id], imgs[k].level_shift);
+      dump = dump || imgs[k].coef_out || imgs[k].scaled_out;
+    }
+  }
+  const int blocks_per_tile = b8 ? wg * bpt : generic_blocks_per_tile(N);
+  int64_t total = 0, pixels = 0;
+  for (auto& d : dimgs) {
+    d.tile0 = static_cast<int32_t>(total);
+    d.ntiles = (d.nblocks + blocks_per_tile - 1) / blocks_per_tile;
+    total += d.ntiles;
+    pixels += static_cast<int64_t>(d.H) * d.W;
+  }
+  if (total >= (int64_t{1} << 31)) return fail(RKLT_E_INVAL, "rklt_plan_create: too many tiles");
+  std::vector<int32_t> tile_img(static_cast<size_t>(total));
+  for (int k = 0; k < n; ++k)
+    for (int t = 0; t < dimgs[k].ntiles; ++t) tile_img[dimgs[k].tile0 + t] = k;
+
+  rklt_plan* p = new (std::nothrow) rklt_plan;
+  if (!p) return fail(RKLT_E_NOMEM, "rklt_plan_create: out of host memory");
+  p->ctx = ctx;
+  p->N = N;
+  p->block8 = b8;
+  p->dump = dump;
+  p->n = n;
+  p->total_tiles = total;
+  p->blocks_per_tile = blocks_per_tile;
+  p->blocks_per_thread = b8 ? bpt : 1;
+  p->wg = b8 ? wg : 256;
+  p->pixels = pixels;
+  hipError_t e = use_device(ctx->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail("hipSetDevice", e);
+  }
+  if (grid_req > 0) {
+    p->grid = grid_req;
+  } else {
+    // enough workgroups to fill every CU several times over
+    const int per_cu = b8 ? (2048 / p->wg) : 8;
+    p->grid = ctx->cus * per_cu;
+  }
+  if (p->grid > total) p->grid = static_cast<int>(total);
+  e = hipMalloc(&p->d_imgs, sizeof(DevImage) * n);
+  if (e == hipSuccess) e = hipMalloc(&p->d_tile_img, sizeof(int32_t) * total);
+  if (e != hipSuccess) {
+    (void)hipFree(p->d_imgs);
+    delete p;
+    return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(p->d_imgs, dimgs.data(), sizeof(DevImage) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_tile_img, tile_img.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(p->d_imgs);
+    (void)hipFree(p->d_tile_img);
+    delete p;
+    return hip_fail("rklt_plan_create: hipMemcpy", e);
+  }
+  *out = p;
+  return RKLT_OK;
+}
+
+rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
+  clear_error();
+  if (!p || !d_res) return fail(RKLT_E_INVAL, "rklt_plan_run: NULL argument");
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.imgs = p->d_imgs;
+  a.tile_img = p->d_tile_img;
+  a.tf = p->ctx->d_table;
+  a.res = d_res;
+  a.total_tiles = static_cast<int32_t>(p->total_tiles);
+  a.blocks_per_tile = p->blocks_per_tile;
+  a.blocks_per_thread = p->blocks_per_thread;
+  a.dump = p->dump ? 1 : 0;
+  hipError_t e = use_device(p->ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  return p->block8 ? launch_block8(a, p->grid, p->wg, stream) : launch_generic(p->N, a, p->grid, stream);
+}
+
+rklt_status rklt_plan_destroy(rklt_plan* p) {
+  clear_error();
+  if (!p) return fail(RKLT_E_INVAL, "rklt_plan_destroy: plan is NULL");
+  (void)use_device(p->ctx->device);
+  (void)hipFree(p->d_imgs);
+  (void)hipFree(p->d_tile_img);
+  delete p;
+  return RKLT_OK;
+}
+
+rklt_status rklt_plan_info(const rklt_plan* p, int64_t* tiles, int32_t* grid_wgs, int64_t* pixels) {
+  clear_error();
+  if (!p) return fail(RKLT_E_INVAL, "rklt_plan_info: plan is NULL");
+  if (tiles) *tiles = p->total_tiles;
+  if (grid_wgs) *grid_wgs = p->grid;
+  if (pixels) *pixels = p->pixels;
+  return RKLT_OK;
+}
+
+rklt_status rklt_copy_bytes(const void* src, void* dst, size_t nbytes, void* stream) {
+  clear_error();
+  if (!src || !dst) return fail(RKLT_E_INVAL, "rklt_copy_bytes: NULL pointer");
+  if (nbytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+    return fail(RKLT_E_INVAL, "rklt_copy_bytes: pointers and size must be 16-byte aligned");
+  return launch_copy(src, dst, nbytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,447 @@
+// HIP kernels of the rounded-KLT block codec for gfx950 (§4.1, Appendix A):
+// forward B = T (A - ell) T^T in exact integers, scaling by s_i s_j and
+// zig-zag zonal truncation in FP32, inverse with T_hat^-1 in FP32, rounding
+// floor(x + 1/2), clipping, and the per-image squared error with PSNR.
+//
+// Two block kernels share the tile / result protocol:
+//   * rklt_block8_kernel: N = 8, level shift 128, int8-range T.  One thread codes whole
+//     8 x 8 blocks in registers: pixels arrive as two 32-bit words per row
+//     (coalesced across the wave: 64 lanes read 512 contiguous bytes per
+//     row), the row transform is v_dot4 on int8 (pixel xor 0x80 = pixel -
+//     128), the column transform v_dot2 on int16 pairs.  Only the
+//     anti-diagonals i + j < D that hold kept coefficients are computed
+//     (D is a template parameter), so truncation removes work instead of
+//     masking it.
+//   * rklt_generic_kernel<N>: any N in {4, 8, 16, 32}; blocks staged in LDS,
+//     one output entry per thread and stage, int32 forward.
+//
+// Work list: a tile is a run of consecutive blocks of one image.  A
+// workgroup loops over tiles (persistent grid for a plan, one tile per
+// workgroup for the plain path), reduces its squared error, adds it to the
+// image's accumulator and counts the tile done; the workgroup that finishes
+// an image's last tile writes SSE, MSE and PSNR and resets the accumulators.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "rklt_internal.h"
+
+namespace rklt {
+namespace {
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// The transform table never changes while a kernel runs: reading it through
+// the constant address space lets every wave-uniform read become a scalar
+// load into SGPRs, even after the kernel has stored pixels.
+typedef const __attribute__((address_space(4))) DevTransform* ConstTransform;
+__device__ __forceinline__ ConstTransform as_constant(const DevTransform* p) {
+  return (ConstTransform)(p);
+}
+
+// Image pointers always address global memory; saying so gives global_load /
+// global_store instead of flat accesses.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* as_global(const T* p) {
+  return (const __attribute__((address_space(1))) T*)(p);
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* as_global(T* p) {
+  return (__attribute__((address_space(1))) T*)(p);
+}
+
+// Position of coefficient (i, j) in the zig-zag scan of an n x n block
+// (§4.1): anti-diagonals t = i + j in order; odd t runs with the row rising,
+// even t with the row falling.
+__host__ __device__ constexpr int zz_rank(int n, int i, int j) {
+  const int t = i + j;
+  const int before = t < n ? t * (t + 1) / 2 : n * n - (2 * n - 1 - t) * (2 * n - t) / 2;
+  const int ilo = t < n ? 0 : t - (n - 1);
+  const int ihi = t < n ? t : n - 1;
+  return before + ((t & 1) ? i - ilo : ihi - i);
+}
+
+__device__ __forceinline__ int dot2(int a, int b, int acc) {
+  return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), acc,
+                                false);
+}
+
+// floor, clip to [0, 255] and place as byte `k` of `word`.
+__device__ __forceinline__ uint32_t pack_pixel(float x, int k, uint32_t word) {
+  const float v = __builtin_amdgcn_fmed3f(floorf(x), 0.0f, 255.0f);
+  return __builtin_amdgcn_cvt_pk_u8_f32(v, k, word);
+}
+
+// Code one 8 x 8 block with level shift 128.  s/d point at its top-left
+// pixel; sxx accumulates sum(x^2) + sum(y^2) and sxy sum(x y) over the
+// original x and the reconstruction y.
+//
+// The scaling and the inverse merge: T_hat^-1 = T^-1 S^-1, so
+//   T_hat^-1 (mask (.) (s s^T) (.) B) T_hat^-T = T^-1 (mask (.) B) T^-T,
+// and both inverse stages take T^-1 directly (the scaled coefficients
+// s_i s_j B_ij are written only by the verification dump).
+//
+// Loop order keeps few table words live: rows i of B outer in the forward
+// column stage (one row of T and one column of T^-1 at a time), output
+// columns n outer in the last inverse stage (one row of T^-1 at a time).
+template <int D, bool DUMP>
+__device__ __forceinline__ void block8(const uint8_t* __restrict__ s, int ps, uint8_t* __restrict__ d,
+                                       int pd, const DevTransform* __restrict__ table, int tid, int r,
+                                       float base, int32_t* __restrict__ coef, float* __restrict__ scaled,
+                                       uint32_t& sxx, uint32_t& sxy) {
+  constexpr int C = D < 8 ? D : 8;  // columns j (and rows i) that hold a kept coefficient
+  // Opaque transform index: the table is read from the scalar cache where it
+  // is used, and loads are not shared (and kept live) across the D variants
+  // or across consecutive blocks.
+  asm volatile("" : "+s"(tid));
+  const ConstTransform tf = as_constant(table + tid);
+
+  u32x2 px[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) px[m] = *as_global(reinterpret_cast<const u32x2*>(s + static_cast<size_t>(m) * ps));
+
+  // Rows: Y[m][j] = sum_n X[m][n] T[j][n], X = pixel - 128 = pixel xor 0x80
+  // (int8 dots), kept as int16 pairs P[p][j] = (Y[2p][j], Y[2p+1][j]).
+  int P[4][C];
+#pragma unroll
+  for (int j = 0; j < C; ++j) {
+    const int t0 = tf->t8[j][0], t1 = tf->t8[j][1];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int m0 = 2 * p, m1 = 2 * p + 1;
+      const int y0 = __builtin_amdgcn_sdot4(static_cast<int>(px[m0].y ^ 0x80808080u), t1,
+                                            __builtin_amdgcn_sdot4(static_cast<int>(px[m0].x ^ 0x80808080u), t0, 0, false),
+                                            false);
+      const int y1 = __builtin_amdgcn_sdot4(static_cast<int>(px[m1].y ^ 0x80808080u), t1,
+                                            __builtin_amdgcn_sdot4(static_cast<int>(px[m1].x ^ 0x80808080u), t0, 0, false),
+                                            false);
+      P[p][j] = static_cast<int>(__builtin_amdgcn_perm(static_cast<uint32_t>(y1), static_cast<uint32_t>(y0), 0x05040100u));
+    }
+  }
+
+  // Columns and first inverse stage:
+  //   B[i][j] = sum_m T[i][m] Y[m][j]                         (int16 dots)
+  //   W[m][j] = sum_{i : (i, j) kept} Ti[m][i] B[i][j]        (FP32, Ti = T^-1)
+  float W[8][C];
+#pragma unroll
+  for (int i = 0; i < C; ++i) {
+    const int jmax = (D - i) < 8 ? (D - i) : 8;
+#pragma unroll
+    for (int j = 0; j < jmax; ++j) {
+      int B = dot2(tf->t16[i][0], P[0][j], 0);
+#pragma unroll
+      for (int p = 1; p < 4; ++p) B = dot2(tf->t16[i][p], P[p][j], B);
+      if (DUMP) {
+        if (coef) as_global(coef)[i * 8 + j] = B;
+        if (scaled) as_global(scaled)[i * 8 + j] = static_cast<float>(B) * tf->w[i * 8 + j];
+      }
+      float c = static_cast<float>(B);
+      // the last anti-diagonal is kept only up to zig-zag position r - 1
+      if (i + j == D - 1 && zz_rank(8, i, j) >= r) c = 0.0f;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) W[m][j] = (i == 0) ? tf->Ti[m * 8 + i] * c : fmaf(tf->Ti[m * 8 + i], c, W[m][j]);
+    }
+  }
+
+  // Second inverse stage, output column n outer:
+  //   A[m][n] = 128 + 1/2 + sum_j W[m][j] Ti[n][j]
+  uint32_t out[8][2];
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      float acc = base;
+#pragma unroll
+      for (int j = 0; j < C; ++j) acc = fmaf(W[m][j], tf->Ti[n * 8 + j], acc);
+      out[m][n >> 2] = pack_pixel(acc, n & 3, (n & 3) ? out[m][n >> 2] : 0u);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const uint32_t lo = out[m][0], hi = out[m][1];
+    if (d) {
+      u32x2 o;
+      o.x = lo;
+      o.y = hi;
+      *as_global(reinterpret_cast<u32x2*>(d + static_cast<size_t>(m) * pd)) = o;
+    }
+    sxx = __builtin_amdgcn_udot4(px[m].x, px[m].x, sxx, false);
+    sxx = __builtin_amdgcn_udot4(px[m].y, px[m].y, sxx, false);
+    sxx = __builtin_amdgcn_udot4(lo, lo, sxx, false);
+    sxx = __builtin_amdgcn_udot4(hi, hi, sxx, false);
+    sxy = __builtin_amdgcn_udot4(px[m].x, lo, sxy, false);
+    sxy = __builtin_amdgcn_udot4(px[m].y, hi, sxy, false);
+  }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Add one tile's squared error to its image and finalise the image when this
+// was its last tile.  Called by one thread.
+__device__ void finish_tile(rklt_result* res, unsigned long long sum, int ntiles, long long npix) {
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(&res->acc);
+  atomicAdd(acc, sum);
+  __threadfence();
+  const unsigned prev = atomicAdd(&res->done, 1u);
+  if (prev + 1u == static_cast<unsigned>(ntiles)) {
+    __threadfence();
+    const unsigned long long sse = atomicExch(acc, 0ull);
+    atomicExch(&res->done, 0u);
+    const float mse = static_cast<float>(sse) / static_cast<float>(npix);
+    res->sse = sse;
+    res->mse = mse;
+    res->psnr_db = sse == 0 ? INFINITY : 10.0f * log10f(65025.0f / mse);
+    res->tiles = static_cast<uint32_t>(ntiles);
+  }
+}
+
+// Workgroup-wide sum of a per-thread value, then finish_tile.
+__device__ __forceinline__ void reduce_and_finish(unsigned long long mine, unsigned long long* red,
+                                                  rklt_result* res, int ntiles, long long npix) {
+  const unsigned long long w = wave_sum(mine);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < static_cast<int>(blockDim.x >> 6); ++k) t += red[k];
+    finish_tile(res, t, ntiles, npix);
+  }
+  __syncthreads();
+}
+
+template <bool DUMP>
+__device__ __forceinline__ void block8_dispatch(int D, const uint8_t* s, int ps, uint8_t* d, int pd,
+                                                const DevTransform* table, int tid, int r, float base,
+                                                int32_t* coef, float* scaled, uint32_t& sxx,
+                                                uint32_t& sxy) {
+#define RKLT_CASE(DD) \
+  case DD:            \
+    block8<DD, DUMP>(s, ps, d, pd, table, tid, r, base, coef, scaled, sxx, sxy); \
+    break;
+  switch (D) {
+    RKLT_CASE(1) RKLT_CASE(2) RKLT_CASE(3) RKLT_CASE(4) RKLT_CASE(5) RKLT_CASE(6) RKLT_CASE(7)
+    RKLT_CASE(8) RKLT_CASE(9) RKLT_CASE(10) RKLT_CASE(11) RKLT_CASE(12) RKLT_CASE(13)
+    RKLT_CASE(14)
+    default:
+      block8<15, DUMP>(s, ps, d, pd, table, tid, r, base, coef, scaled, sxx, sxy);
+      break;
+  }
+#undef RKLT_CASE
+}
+
+__global__ __launch_bounds__(256) void rklt_block8_kernel(KArgs a) {
+  __shared__ unsigned long long red[4];
+  for (int tile = blockIdx.x; tile < a.total_tiles; tile += gridDim.x) {
+    const int ii = a.imgs ? __builtin_amdgcn_readfirstlane(a.tile_img[tile]) : 0;
+    const DevImage* im = a.imgs ? a.imgs + ii : &a.one;
+    const int tid = __builtin_amdgcn_readfirstlane(im->tid);
+    const int b0 = (tile - im->tile0) * a.blocks_per_tile;
+    const int nblocks = im->nblocks, bw = im->bw, ps = im->ps, pd = im->pd;
+    const int r = im->r, D = a.dump ? 15 : im->D;
+    const float base = 128.5f;
+    uint32_t sxx = 0, sxy = 0;
+    for (int k = 0; k < a.blocks_per_thread; ++k) {
+      const int b = b0 + k * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
+      if (b < nblocks) {
+        const int by = b / bw, bx = b - by * bw;
+        const uint8_t* s = im->src + static_cast<size_t>(by) * 8 * ps + bx * 8;
+        uint8_t* d = im->dst ? im->dst + static_cast<size_t>(by) * 8 * pd + bx * 8 : nullptr;
+        if (a.dump) {
+          int32_t* coef = im->coef ? im->coef + static_cast<size_t>(b) * 64 : nullptr;
+          float* scaled = im->scaled ? im->scaled + static_cast<size_t>(b) * 64 : nullptr;
+          block8<15, true>(s, ps, d, pd, a.tf, tid, r, base, coef, scaled, sxx, sxy);
+        } else {
+          block8_dispatch<false>(D, s, ps, d, pd, a.tf, tid, r, base, nullptr, nullptr, sxx, sxy);
+        }
+      }
+    }
+    const uint32_t mine = sxx - 2u * sxy;
+    reduce_and_finish(mine, red, a.res + ii, im->ntiles, static_cast<long long>(im->H) * im->W);
+  }
+}
+
+// Blocks per inner iteration and pixels per thread of the generic kernel
+// (256 threads).
+template <int N>
+struct GenericShape {
+  static constexpr int NN = N * N;
+  static constexpr int BPI = NN >= 256 ? 1 : 256 / NN;
+  static constexpr int PPT = NN >= 256 ? NN / 256 : 1;
+  static constexpr int ITEMS = BPI * NN;
+  static constexpr int TILE_BLOCKS = 4096 / NN;  // 4096 pixels per tile
+};
+
+template <int N>
+__global__ __launch_bounds__(256) void rklt_generic_kernel(KArgs a) {
+  using S = GenericShape<N>;
+  constexpr int NN = S::NN, BPI = S::BPI, PPT = S::PPT, ITEMS = S::ITEMS;
+  __shared__ int sX[ITEMS];
+  __shared__ int sY[ITEMS];
+  __shared__ float sC[ITEMS];
+  __shared__ float sW[ITEMS];
+  __shared__ int sT[NN];
+  __shared__ float sG[NN];
+  __shared__ float sw[NN];
+  __shared__ int srank[NN];
+  __shared__ unsigned long long red[4];
+  int loaded = -1;
+  for (int tile = blockIdx.x; tile < a.total_tiles; tile += gridDim.x) {
+    const int ii = a.imgs ? a.tile_img[tile] : 0;
+    const DevImage* im = a.imgs ? a.imgs + ii : &a.one;
+    const DevTransform* tf = a.tf + im->tid;
+    if (im->tid != loaded) {
+      __syncthreads();
+      for (int k = threadIdx.x; k < NN; k += blockDim.x) {
+        sT[k] = tf->T[k];
+        sG[k] = tf->G[k];
+        sw[k] = tf->w[k];
+        srank[k] = tf->rank[k];
+      }
+      __syncthreads();
+      loaded = im->tid;
+    }
+    const int b0 = (tile - im->tile0) * a.blocks_per_tile;
+    const int nblocks = im->nblocks, bw = im->bw, r = im->r, ell = im->ell;
+    const float base = static_cast<float>(ell) + 0.5f;
+    unsigned long long sse = 0;
+    for (int it = 0; it * BPI < a.blocks_per_tile; ++it) {
+      const int bbase = b0 + it * BPI;
+      if (bbase >= nblocks) break;
+      int orig[PPT];
+      // pixels: entry (q, m, n) = idx -> block bbase + q, row m, column n
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const int idx = threadIdx.x + e * 256;
+        const int q = idx / NN, pos = idx % NN, m = pos / N, n = pos % N;
+        const int b = bbase + q;
+        int v = 0;
+        orig[e] = 0;
+        if (b < nblocks) {
+          const int by = b / bw, bx = b - by * bw;
+          const int p = im->src[static_cast<size_t>(by * N + m) * im->ps + bx * N + n];
+          orig[e] = p;
+          v = p - ell;
+        }
+        sX[idx] = v;
+      }
+      __syncthreads();
+      // rows: Y[q][m][j] = sum_n X[q][m][n] T[j][n]
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const int idx = threadIdx.x + e * 256;
+        const int q = idx / NN, pos = idx % NN, m = pos / N, j = pos % N;
+        int y = 0;
+#pragma unroll 8
+        for (int n = 0; n < N; ++n) y += sX[q * NN + m * N + n] * sT[j * N + n];
+        sY[idx] = y;
+      }
+      __syncthreads();
+      // columns: B[q][i][j] = sum_m T[i][m] Y[q][m][j]; scale and keep
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const int idx = threadIdx.x + e * 256;
+        const int q = idx / NN, pos = idx % NN, i = pos / N, j = pos % N;
+        int B = 0;
+#pragma unroll 8
+        for (int m = 0; m < N; ++m) B += sT[i * N + m] * sY[q * NN + m * N + j];
+        const int b = bbase + q;
+        if (a.dump && b < nblocks) {
+          if (im->coef) im->coef[static_cast<size_t>(b) * NN + pos] = B;
+          if (im->scaled) im->scaled[static_cast<size_t>(b) * NN + pos] = static_cast<float>(B) * sw[pos];
+        }
+        sC[idx] = srank[pos] < r ? static_cast<float>(B) * sw[pos] : 0.0f;
+      }
+      __syncthreads();
+      // inverse, columns: W[q][m][j] = sum_i G[m][i] Bh[q][i][j]
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const int idx = threadIdx.x + e * 256;
+        const int q = idx / NN, pos = idx % NN, m = pos / N, j = pos % N;
+        float w = 0.0f;
+#pragma unroll 8
+        for (int i = 0; i < N; ++i) w = fmaf(sG[m * N + i], sC[q * NN + i * N + j], w);
+        sW[idx] = w;
+      }
+      __syncthreads();
+      // inverse, rows: A[q][m][n] = ell + 1/2 + sum_j W[q][m][j] G[n][j]
+#pragma unroll
+      for (int e = 0; e < PPT; ++e) {
+        const int idx = threadIdx.x + e * 256;
+        const int q = idx / NN, pos = idx % NN, m = pos / N, n = pos % N;
+        float acc = base;
+#pragma unroll 8
+        for (int j = 0; j < N; ++j) acc = fmaf(sW[q * NN + m * N + j], sG[n * N + j], acc);
+        const int b = bbase + q;
+        if (b < nblocks) {
+          const int v = static_cast<int>(__builtin_amdgcn_fmed3f(floorf(acc), 0.0f, 255.0f));
+          const int by = b / bw, bx = b - by * bw;
+          if (im->dst) im->dst[static_cast<size_t>(by * N + m) * im->pd + bx * N + n] = static_cast<uint8_t>(v);
+          const int diff = orig[e] - v;
+          sse += static_cast<unsigned long long>(diff * diff);
+        }
+      }
+      __syncthreads();
+    }
+    reduce_and_finish(sse, red, a.res + ii, im->ntiles, static_cast<long long>(im->H) * im->W);
+  }
+}
+
+__global__ __launch_bounds__(256) void rklt_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                        size_t n) {
+  const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  for (size_t i = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+rklt_status launched(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RKLT_E_HIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+  return RKLT_OK;
+}
+
+}  // namespace
+
+int generic_blocks_per_tile(int N) {
+  switch (N) {
+    case 4: return GenericShape<4>::TILE_BLOCKS;
+    case 8: return GenericShape<8>::TILE_BLOCKS;
+    case 16: return GenericShape<16>::TILE_BLOCKS;
+    case 32: return GenericShape<32>::TILE_BLOCKS;
+    default: return 0;
+  }
+}
+
+rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream) {
+  hipLaunchKernelGGL(rklt_block8_kernel, dim3(grid), dim3(wg), 0, static_cast<hipStream_t>(stream), a);
+  return launched("rklt_block8_kernel");
+}
+
+rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream) {
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (N) {
+    case 4: hipLaunchKernelGGL(rklt_generic_kernel<4>, dim3(grid), dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(rklt_generic_kernel<8>, dim3(grid), dim3(256), 0, st, a); break;
+    case 16: hipLaunchKernelGGL(rklt_generic_kernel<16>, dim3(grid), dim3(256), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(rklt_generic_kernel<32>, dim3(grid), dim3(256), 0, st, a); break;
+    default: return fail(RKLT_E_INVAL, "generic kernel: N=%d not supported", N);
+  }
+  return launched("rklt_generic_kernel");
+}
+
+rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream) {
+  const size_t n = nbytes / 16;
+  if (n == 0) return RKLT_OK;
+  size_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(rklt_copy_kernel, dim3(static_cast<unsigned>(grid)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), static_cast<const uint4*>(src), static_cast<uint4*>(dst), n);
+  return launched("rklt_copy_kernel");
+}
+
+}  // namespace rklt

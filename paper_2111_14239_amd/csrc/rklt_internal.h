@@ -1,0 +1,76 @@
+// Internal declarations of librklt: error reporting, the device-side
+// transform record and work-list entries shared by the host code and the
+// kernels.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+
+#include "rklt.h"
+
+namespace rklt {
+
+// Record `code` with a printf-style message in the thread-local error slot.
+rklt_status fail(rklt_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out);
+rklt_status zigzag(int N, int32_t* order);
+
+constexpr int kMaxTransforms = 256;
+
+// Device copy of one transform (one entry of a context's table).  Everything
+// the kernels read about T, in the layouts they read it in.
+struct alignas(256) DevTransform {
+  int32_t N, flags, max_abs, max_row_l1;
+  int32_t sig[RKLT_MAX_N];       // sigma_i = sum_j T_ij (row sums)
+  int32_t t8[8][2];              // N = 8: row j of T as int8x4 words, n = 0..3 | 4..7
+  int32_t t16[8][4];             // N = 8: row i of T as int16x2 words, (m, m+1) pairs
+  float w[RKLT_MAX_N * RKLT_MAX_N];     // s_i s_j at i*N + j
+  float G[RKLT_MAX_N * RKLT_MAX_N];     // T_hat^-1 at m*N + i
+  float Ti[RKLT_MAX_N * RKLT_MAX_N];    // T^-1 = T_hat^-1 S at m*N + i
+  int32_t T[RKLT_MAX_N * RKLT_MAX_N];   // T at i*N + j
+  int32_t rank[RKLT_MAX_N * RKLT_MAX_N];  // zig-zag position of (i, j)
+};
+
+// One image of a launch (device memory for a plan, a kernel argument for the
+// plain path).
+struct DevImage {
+  const uint8_t* src;
+  uint8_t* dst;
+  int32_t* coef;
+  float* scaled;
+  int32_t H, W, ps, pd;
+  int32_t tid, r, ell, D;  // D: anti-diagonals i + j < D hold every kept coefficient
+  int32_t bw, nblocks, tile0, ntiles;
+};
+
+struct KArgs {
+  const DevImage* imgs;      // plan images, or nullptr for the plain path
+  const int32_t* tile_img;   // image index of every tile (plan only)
+  const DevTransform* tf;    // context transform table
+  rklt_result* res;          // one per image
+  int32_t total_tiles;
+  int32_t blocks_per_tile;
+  int32_t blocks_per_thread;  // N = 8 path
+  int32_t dump;               // write coefficient dumps
+  DevImage one;               // the image of the plain path
+};
+
+// Number of anti-diagonals i + j < D that contain the first r zig-zag
+// positions of an N x N block.
+inline int diagonals_for(int N, int r) {
+  int D = 0, covered = 0;
+  while (covered < r) {
+    covered += (D < N) ? D + 1 : 2 * N - 1 - D;
+    ++D;
+  }
+  return D;
+}
+
+// Kernel launchers (codec.hip).
+rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream);
+rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream);
+rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
+int generic_blocks_per_tile(int N);
+
+}  // namespace rklt

@@ -1,0 +1,199 @@
+// Host-side design of the rounded KLT (FP64): §2.1 (KLT of a first-order
+// Markov signal), §2.2 Eq. (1) (scaling S), §2.3 Eq. (2) (T = round(alpha K))
+// and the zig-zag scan of §4.1.  Pure C++; no HIP.
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "rklt.h"
+#include "rklt_internal.h"
+
+namespace rklt {
+
+namespace {
+
+// Root function of the §2.1 frequency equation
+//   tan(N w) = -(1 - rho^2) sin w / ((1 + rho^2) cos w - 2 rho)
+// with both denominators multiplied out, and its derivative in w.
+struct FreqEq {
+  int N;
+  double a, b;  // a = 1 + rho^2, b = 1 - rho^2
+  double rho;
+  double f(double w) const {
+    return std::sin(N * w) * (a * std::cos(w) - 2.0 * rho) + b * std::sin(w) * std::cos(N * w);
+  }
+  double df(double w) const {
+    const double sN = std::sin(N * w), cN = std::cos(N * w);
+    const double s1 = std::sin(w), c1 = std::cos(w);
+    return N * cN * (a * c1 - 2.0 * rho) - sN * a * s1 + b * (c1 * cN - N * s1 * sN);
+  }
+};
+
+// Safeguarded Newton iteration on [lo, hi], where f changes sign: a Newton
+// step is taken when it stays inside the current bracket, a bisection step
+// otherwise; the bracket shrinks every iteration.
+double solve_bracketed(const FreqEq& eq, double lo, double hi) {
+  double flo = eq.f(lo);
+  double fhi = eq.f(hi);
+  if (flo == 0.0) return lo;
+  if (fhi == 0.0) return hi;
+  double x = 0.5 * (lo + hi);
+  for (int it = 0; it < 200; ++it) {
+    const double fx = eq.f(x);
+    if (fx == 0.0) return x;
+    if ((fx < 0.0) == (flo < 0.0)) {
+      lo = x;
+      flo = fx;
+    } else {
+      hi = x;
+    }
+    if (hi - lo <= 4e-16 * std::fabs(hi)) break;
+    const double dfx = eq.df(x);
+    double nx = (dfx != 0.0) ? x - fx / dfx : lo - 1.0;
+    if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+    if (nx == x) break;
+    x = nx;
+  }
+  return x;
+}
+
+// Gauss-Jordan inverse with partial pivoting, FP64.  Returns false when a
+// pivot is negligible against the row scale (singular matrix).
+bool invert(int n, const double* A, double* inv) {
+  double M[RKLT_MAX_N][2 * RKLT_MAX_N];
+  double scale = 0.0;
+  for (int i = 0; i < n; ++i) {
+    for (int j = 0; j < n; ++j) {
+      M[i][j] = A[i * n + j];
+      M[i][n + j] = (i == j) ? 1.0 : 0.0;
+      scale = std::fmax(scale, std::fabs(A[i * n + j]));
+    }
+  }
+  if (scale == 0.0) return false;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int i = c + 1; i < n; ++i)
+      if (std::fabs(M[i][c]) > std::fabs(M[p][c])) p = i;
+    if (std::fabs(M[p][c]) <= 1e-10 * scale) return false;
+    if (p != c)
+      for (int j = 0; j < 2 * n; ++j) std::swap(M[p][j], M[c][j]);
+    const double piv = M[c][c];
+    for (int j = 0; j < 2 * n; ++j) M[c][j] /= piv;
+    for (int i = 0; i < n; ++i) {
+      if (i == c || M[i][c] == 0.0) continue;
+      const double f = M[i][c];
+      for (int j = 0; j < 2 * n; ++j) M[i][j] -= f * M[c][j];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) inv[i * n + j] = M[i][n + j];
+  return true;
+}
+
+}  // namespace
+
+rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out) {
+  if (!out) return fail(RKLT_E_INVAL, "rklt_build_transform: out is NULL");
+  if (N < 2 || N > RKLT_MAX_N)
+    return fail(RKLT_E_INVAL, "rklt_build_transform: N=%d outside 2..%d", N, RKLT_MAX_N);
+  if (!(rho > 0.0 && rho < 1.0))
+    return fail(RKLT_E_INVAL, "rklt_build_transform: rho=%g outside (0, 1)", rho);
+  if (!(alpha > 0.0) || !std::isfinite(alpha))
+    return fail(RKLT_E_INVAL, "rklt_build_transform: alpha=%g is not positive and finite", alpha);
+
+  std::memset(out, 0, sizeof(*out));
+  out->N = N;
+  out->rho = rho;
+  out->alpha = alpha;
+
+  // §2.1: one frequency in each open interval (k pi / N, (k+1) pi / N).
+  // w = 0 and w = pi are trivial zeros of the cleared equation, so the two
+  // outer brackets start a little way inside.
+  const FreqEq eq{N, 1.0 + rho * rho, 1.0 - rho * rho, rho};
+  double omega[RKLT_MAX_N], lambda[RKLT_MAX_N];
+  const double step = M_PI / N;
+  for (int k = 0; k < N; ++k) {
+    double lo = k * step, hi = (k + 1) * step;
+    if (k == 0) lo += 1e-7 * step;
+    if (k == N - 1) hi -= 1e-7 * step;
+    omega[k] = solve_bracketed(eq, lo, hi);
+    lambda[k] = (1.0 - rho * rho) / (1.0 + rho * rho - 2.0 * rho * std::cos(omega[k]));
+  }
+
+  // §2.1: basis vector k sampled at n (row k of K), with the frequency and the
+  // phase indexed by the basis index k.
+  for (int k = 0; k < N; ++k) {
+    const double amp = std::sqrt(2.0 / (N + lambda[k]));
+    for (int n = 0; n < N; ++n)
+      out->K[k * N + n] = amp * std::sin(omega[k] * (n - 0.5 * (N - 1)) + 0.5 * (k + 1) * M_PI);
+  }
+
+  // Eq. (2): T = round(alpha K), round(x) = floor(x + 1/2).
+  int max_abs = 0, max_l1 = 0;
+  bool adds_only = true;
+  for (int i = 0; i < N; ++i) {
+    int l1 = 0;
+    for (int j = 0; j < N; ++j) {
+      const double v = std::floor(alpha * out->K[i * N + j] + 0.5);
+      if (std::fabs(v) > 1e6)
+        return fail(RKLT_E_RANGE, "rklt_build_transform: alpha=%g gives entries beyond 1e6", alpha);
+      const int t = static_cast<int>(v);
+      out->T[i * N + j] = t;
+      const int a = t < 0 ? -t : t;
+      max_abs = a > max_abs ? a : max_abs;
+      l1 += a;
+      if (a > 1) adds_only = false;
+    }
+    max_l1 = l1 > max_l1 ? l1 : max_l1;
+  }
+  out->max_abs = max_abs;
+  out->max_row_l1 = max_l1;
+
+  // Eq. (1): d = diag(T T^T), s = d^(-1/2).  T T^T diagonal <=> orthogonal rows.
+  bool orthogonal = true;
+  for (int i = 0; i < N; ++i) {
+    for (int k = 0; k < N; ++k) {
+      int64_t dot = 0;
+      for (int j = 0; j < N; ++j)
+        dot += static_cast<int64_t>(out->T[i * N + j]) * out->T[k * N + j];
+      if (i == k) out->d[i] = dot;
+      else if (dot != 0) orthogonal = false;
+    }
+    if (out->d[i] == 0)
+      return fail(RKLT_E_SINGULAR,
+                  "rklt_build_transform: row %d of round(alpha K) is zero (N=%d rho=%g alpha=%g)", i,
+                  N, rho, alpha);
+    out->s[i] = 1.0 / std::sqrt(static_cast<double>(out->d[i]));
+  }
+  out->flags = (orthogonal ? RKLT_ORTHOGONAL : 0u) | (adds_only ? RKLT_ADDS_ONLY : 0u);
+
+  // G = T_hat^-1 with T_hat = S T.
+  double That[RKLT_MAX_N * RKLT_MAX_N];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) That[i * N + j] = out->s[i] * out->T[i * N + j];
+  if (!invert(N, That, out->G))
+    return fail(RKLT_E_SINGULAR, "rklt_build_transform: round(alpha K) is singular (N=%d rho=%g alpha=%g)",
+                N, rho, alpha);
+  return RKLT_OK;
+}
+
+rklt_status zigzag(int N, int32_t* order) {
+  if (!order) return fail(RKLT_E_INVAL, "rklt_zigzag: order is NULL");
+  if (N < 1 || N > RKLT_MAX_N) return fail(RKLT_E_INVAL, "rklt_zigzag: N=%d outside 1..%d", N, RKLT_MAX_N);
+  // Walk the anti-diagonals i + j = t in turn.  On odd t the scan moves
+  // down-left (row i rising), on even t up-right (row i falling); this starts
+  // (0,0) -> (0,1) -> (1,0) -> (2,0) as in JPEG.
+  int k = 0;
+  for (int t = 0; t <= 2 * (N - 1); ++t) {
+    const int ilo = t < N ? 0 : t - (N - 1);
+    const int ihi = t < N ? t : N - 1;
+    if (t & 1) {
+      for (int i = ilo; i <= ihi; ++i) order[k++] = i * N + (t - i);
+    } else {
+      for (int i = ihi; i >= ilo; --i) order[k++] = i * N + (t - i);
+    }
+  }
+  return RKLT_OK;
+}
+
+}  // namespace rklt
