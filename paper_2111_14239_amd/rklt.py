@@ -65,6 +65,10 @@ class Tuning(C.Structure):
 
 
 def _load():
+    # torch brings its own HIP runtime (same soname as /opt/rocm's).  Loading
+    # torch first makes this library bind to that runtime, so that torch's
+    # device pointers and stream handles are valid in both.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(python -m paper_2111_14239_amd.build_lib)")

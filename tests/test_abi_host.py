@@ -128,3 +128,13 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert L.rklt_copy_bytes(None, None, 16, None) == rklt.E_INVAL
     h = C.c_void_p()
     assert L.rklt_plan_create(None, None, 0, None, C.byref(h)) == rklt.E_INVAL
+
+
+def test_library_uses_torchs_hip_runtime():
+    # torch's device pointers and stream handles are only valid in the HIP
+    # runtime torch itself loaded; the binding must make the library bind to it
+    import torch
+    maps = open("/proc/self/maps").read()
+    hips = {line.split()[-1] for line in maps.splitlines() if "libamdhip64" in line}
+    assert len(hips) == 1, hips
+    assert os.path.dirname(torch.__file__) in next(iter(hips))
