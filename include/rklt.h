@@ -95,17 +95,18 @@ typedef struct {
  * ones); scaled_out is (s s^T) (.) B before zonal masking.  Writing them adds
  * 4 bytes per pixel each, so they are meant for verification only. */
 
-/* Per-image result (device memory, written by the codec).  acc and done are
- * the codec's own accumulators: the array must be zero-filled once before its
- * first use, and every completed call leaves them at zero again, so the same
- * array can be reused without clearing it. */
+/* Per-image result (device memory, written by the codec).  `acc` is the
+ * codec's own accumulator (tile count above bit 48, running SSE below): the
+ * array must be zero-filled once before its first use, and every completed
+ * call leaves `acc` at zero again, so the same array can be reused without
+ * clearing it.  Calls that share a results array must not overlap. */
 typedef struct {
-  uint64_t sse;    /* sum of squared pixel errors (exact)                       */
-  float mse;       /* sse / (H W) in FP32                                       */
-  float psnr_db;   /* 10 log10(255^2 / mse) in FP32, +inf when sse == 0         */
-  uint64_t acc;    /* internal: running SSE while the call is in flight         */
-  uint32_t done;   /* internal: finished tiles while the call is in flight      */
-  uint32_t tiles;  /* number of tiles the image was coded in (set when final)   */
+  uint64_t sse;      /* sum of squared pixel errors (exact)                     */
+  float mse;         /* sse / (H W) in FP32                                     */
+  float psnr_db;     /* 10 log10(255^2 / mse) in FP32, +inf when sse == 0       */
+  uint64_t acc;      /* internal: running tile count and SSE of a call          */
+  uint32_t tiles;    /* number of tiles the image was coded in (set when final) */
+  uint32_t reserved;
 } rklt_result;
 
 /* Launch shape of the block kernels.  Zero fields take the defaults. */
@@ -152,6 +153,14 @@ rklt_status rklt_ctx_destroy(rklt_ctx* ctx);
  * full), E_HIP. */
 rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32_t* id_out);
 
+/* Whether the N = 8 register kernel reconstructs transform `id` exactly:
+ * T^-1 = adj / den with integer adj small enough that every step of the
+ * inverse is exact, so reconstructed pixels equal floor(x + 1/2) of the exact
+ * rational x (ties included).  Otherwise (*exact = 0, *den = 0) the inverse
+ * runs in FP32 and a pixel may differ by one level where x is within about
+ * 1e-3 of a rounding tie.  Errors: E_INVAL (NULL ctx, unknown id). */
+rklt_status rklt_ctx_transform_exact(rklt_ctx* ctx, int32_t id, int32_t* exact, int64_t* den);
+
 /* ---- codec -------------------------------------------------------------- */
 
 /* Plain path: code one image with one kernel launch on `stream` (§4.1).
@@ -176,6 +185,11 @@ rklt_status rklt_plan_destroy(rklt_plan* plan);
 /* Number of tiles and of workgroups the plan launches (for reporting). */
 rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_wgs,
                            int64_t* pixels);
+/* A plan launches one kernel per kernel class among its images: the N = 8
+ * register kernel (level shift 128, |T_ij| <= 127, 128 * max row L1 <= 32767)
+ * and the generic LDS kernel (everything else).  Reports the number of
+ * launches per run and how many images take the register kernel. */
+rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* block8_images);
 
 /* ---- measurement -------------------------------------------------------- */
 

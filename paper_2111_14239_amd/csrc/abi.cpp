@@ -21,19 +21,24 @@ struct rklt_ctx {
   std::mutex mu;
 };
 
-struct rklt_plan {
-  rklt_ctx* ctx = nullptr;
-  int N = 0;
+// One launch of a plan: the images of one kernel class.
+struct PlanPart {
   bool block8 = false;
-  bool dump = false;
   int n = 0;
   rklt::DevImage* d_imgs = nullptr;
   int32_t* d_tile_img = nullptr;
   int64_t total_tiles = 0;
-  int blocks_per_tile = 0;
-  int blocks_per_thread = 1;
   int wg = 256;
   int grid = 0;
+};
+
+struct rklt_plan {
+  rklt_ctx* ctx = nullptr;
+  int N = 0;
+  bool dump = false;
+  int n = 0;
+  int nparts = 0;
+  PlanPart parts[2];
   int64_t pixels = 0;
 };
 
@@ -43,7 +48,7 @@ namespace {
 thread_local char g_error[512] = "";
 
 constexpr int kDefaultWg = 256;
-constexpr int kDefaultBpt = 2;
+constexpr int kDefaultBpt = 4;
 
 bool block8_fits(const DevTransform& t, int ell) {
   // level shift 128 (pixel xor 0x80), int8 entries for the row dots and
@@ -110,6 +115,15 @@ rklt_status check_image(rklt_ctx* ctx, const rklt_image& im, int index, DevImage
   d.nblocks = (im.H / N) * (im.W / N);
   *N_out = N;
   return RKLT_OK;
+}
+
+// Blocks per tile for one image: the launch's tile size, grown (in steps of
+// `unit` blocks) until the image has at most kMaxTilesPerImage tiles.
+int image_tile_blocks(const DevImage& d, int base, int unit) {
+  int tb = base;
+  const int64_t need = (static_cast<int64_t>(d.nblocks) + kMaxTilesPerImage - 1) / kMaxTilesPerImage;
+  if (tb < need) tb = static_cast<int>((need + unit - 1) / unit * unit);
+  return tb;
 }
 
 rklt_status check_tuning(const rklt_tuning* tu, int* wg, int* bpt, int* grid) {
@@ -249,6 +263,59 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
     }
     dt.sig[i] = sig;
   }
+  if (N == 8) {
+    // Exact inverse for the N = 8 register kernel, with the bounds that keep
+    // every inverse stage exact in FP32: |B_ij| <= 128 L1_i L1_j (pixels - 128
+    // lie in [-128, 127]); every product and partial sum of W = adj B and of
+    // Out = W adj^T is bounded by wmax and omax, which must stay below 2^24
+    // so that each FMA on these integers is exact; and half the spacing
+    // 1/den^2 of the rationals Out/den^2 must exceed twice the FP32 rounding
+    // error of Out/den^2 + 128 (<= 4e-5).
+    int64_t adj[64], den = 0;
+    if (exact_inverse(8, t->T, adj, &den)) {
+      double L1[8];
+      for (int i = 0; i < 8; ++i) {
+        L1[i] = 0;
+        for (int j = 0; j < 8; ++j) L1[i] += std::abs(t->T[i * 8 + j]);
+      }
+      double wmax = 0, omax = 0, amax = 0;
+      for (int m = 0; m < 8; ++m) {
+        for (int j = 0; j < 8; ++j) {
+          double w = 0;
+          for (int i = 0; i < 8; ++i) w += std::fabs(static_cast<double>(adj[m * 8 + i])) * 128.0 * L1[i] * L1[j];
+          wmax = std::fmax(wmax, w);
+        }
+        for (int n = 0; n < 8; ++n) {
+          double o = 0;
+          for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j)
+              o += std::fabs(static_cast<double>(adj[m * 8 + i])) * std::fabs(static_cast<double>(adj[n * 8 + j])) *
+                   128.0 * L1[i] * L1[j];
+          omax = std::fmax(omax, o);
+        }
+        for (int i = 0; i < 8; ++i) amax = std::fmax(amax, std::fabs(static_cast<double>(adj[m * 8 + i])));
+      }
+      const double d2 = static_cast<double>(den) * static_cast<double>(den);
+      const double delta = (den % 2 == 0) ? 0.5 / d2 : 0.25 / d2;
+      const bool ok = wmax < 16777216.0 && omax < 16777216.0 && amax < 16777216.0 && delta > 8e-5;
+      if (ok) {
+        dt.exact = 1;  // (exact = 0 and the FP32 constants are set below otherwise)
+        dt.den = static_cast<int32_t>(den);
+        dt.inv_den2 = static_cast<float>(1.0 / d2);
+        dt.bias = static_cast<float>(128.0 + delta);
+        for (int k = 0; k < 64; ++k) {
+          dt.adj[k] = static_cast<int32_t>(adj[k]);
+          dt.fadj[k] = static_cast<float>(adj[k]);
+        }
+      }
+    }
+  }
+  if (N == 8 && !dt.exact) {
+    dt.den = 0;
+    dt.inv_den2 = 1.0f;
+    dt.bias = 128.0f + 1.0f / 4096.0f;
+    for (int k = 0; k < 64; ++k) dt.fadj[k] = dt.Ti[k];
+  }
   if (N == 8 && max_abs <= 127) {
     for (int j = 0; j < 8; ++j) {
       for (int h = 0; h < 2; ++h) {
@@ -299,10 +366,11 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     if ((st = check_image(ctx, *img, 0, &a.one, &N))) return st;
     a.dump = (img->coef_out || img->scaled_out) ? 1 : 0;
     const bool b8 = block8_fits(ctx->host[img->transform_id], img->level_shift);
-    a.blocks_per_thread = b8 ? bpt : 1;
-    a.blocks_per_tile = b8 ? wg * bpt : generic_blocks_per_tile(N);
     a.one.tile0 = 0;
-    a.one.ntiles = (a.one.nblocks + a.blocks_per_tile - 1) / a.blocks_per_tile;
+    a.one.slot = 0;
+    a.one.tile_blocks = b8 ? image_tile_blocks(a.one, wg * bpt, wg)
+                           : image_tile_blocks(a.one, generic_blocks_per_tile(N), generic_blocks_per_iteration(N));
+    a.one.ntiles = (a.one.nblocks + a.one.tile_blocks - 1) / a.one.tile_blocks;
     a.total_tiles = a.one.ntiles;
     a.tf = ctx->d_table;
     a.res = d_res;
@@ -313,6 +381,55 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
   }
 }
 
+namespace {
+
+void free_part(PlanPart& q) {
+  (void)hipFree(q.d_imgs);
+  (void)hipFree(q.d_tile_img);
+  q.d_imgs = nullptr;
+  q.d_tile_img = nullptr;
+}
+
+// Tile the images of one kernel class and upload the work list.
+rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, bool b8, int wg, int bpt, int grid_req, int N,
+                       PlanPart* q) {
+  const int base = b8 ? wg * bpt : generic_blocks_per_tile(N);
+  const int unit = b8 ? wg : generic_blocks_per_iteration(N);
+  int64_t total = 0;
+  for (auto& d : imgs) {
+    d.tile0 = static_cast<int32_t>(total);
+    d.tile_blocks = image_tile_blocks(d, base, unit);
+    d.ntiles = (d.nblocks + d.tile_blocks - 1) / d.tile_blocks;
+    total += d.ntiles;
+  }
+  if (total >= (int64_t{1} << 31)) return fail(RKLT_E_INVAL, "rklt_plan_create: too many tiles");
+  std::vector<int32_t> tile_img(static_cast<size_t>(total));
+  for (size_t k = 0; k < imgs.size(); ++k)
+    for (int t = 0; t < imgs[k].ntiles; ++t) tile_img[imgs[k].tile0 + t] = static_cast<int32_t>(k);
+  q->block8 = b8;
+  q->n = static_cast<int>(imgs.size());
+  q->total_tiles = total;
+  q->wg = b8 ? wg : 256;
+  // enough workgroups to fill every CU several times over
+  q->grid = grid_req > 0 ? grid_req : ctx->cus * (b8 ? 2048 / q->wg : 8);
+  if (q->grid > total) q->grid = static_cast<int>(total);
+  hipError_t e = hipMalloc(&q->d_imgs, sizeof(DevImage) * imgs.size());
+  if (e == hipSuccess) e = hipMalloc(&q->d_tile_img, sizeof(int32_t) * total);
+  if (e != hipSuccess) {
+    free_part(*q);
+    return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(q->d_imgs, imgs.data(), sizeof(DevImage) * imgs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(q->d_tile_img, tile_img.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_part(*q);
+    return hip_fail("rklt_plan_create: hipMemcpy", e);
+  }
+  return RKLT_OK;
+}
+
+}  // namespace
+
 rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, const rklt_tuning* tuning,
                              rklt_plan** out) {
   clear_error();
@@ -321,74 +438,47 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
   int wg, bpt, grid_req;
   rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
   if (st) return st;
-  std::vector<DevImage> dimgs(static_cast<size_t>(n));
+  std::vector<DevImage> by_class[2];  // [0] generic kernel, [1] N = 8 register kernel
   int N = 0;
-  bool b8 = true, dump = false;
+  bool dump = false;
+  int64_t pixels = 0;
   {
     std::lock_guard<std::mutex> lock(ctx->mu);
     for (int k = 0; k < n; ++k) {
+      DevImage d;
       int Nk = 0;
-      if ((st = check_image(ctx, imgs[k], k, &dimgs[k], &Nk))) return st;
+      if ((st = check_image(ctx, imgs[k], k, &d, &Nk))) return st;
       if (k == 0) N = Nk;
       else if (Nk != N)
         return fail(RKLT_E_INVAL, "image %d: N=%d differs from N=%d of image 0 (one N per plan)", k, Nk, N);
-      b8 = b8 && block8_fits(ctx->host[imgs[k].transform_id], imgs[k].level_shift);
+      d.slot = k;
+      const bool b8 = block8_fits(ctx->host[imgs[k].transform_id], imgs[k].level_shift);
+      by_class[b8 ? 1 : 0].push_back(d);
       dump = dump || imgs[k].coef_out || imgs[k].scaled_out;
+      pixels += static_cast<int64_t>(imgs[k].H) * imgs[k].W;
     }
   }
-  const int blocks_per_tile = b8 ? wg * bpt : generic_blocks_per_tile(N);
-  int64_t total = 0, pixels = 0;
-  for (auto& d : dimgs) {
-    d.tile0 = static_cast<int32_t>(total);
-    d.ntiles = (d.nblocks + blocks_per_tile - 1) / blocks_per_tile;
-    total += d.ntiles;
-    pixels += static_cast<int64_t>(d.H) * d.W;
-  }
-  if (total >= (int64_t{1} << 31)) return fail(RKLT_E_INVAL, "rklt_plan_create: too many tiles");
-  std::vector<int32_t> tile_img(static_cast<size_t>(total));
-  for (int k = 0; k < n; ++k)
-    for (int t = 0; t < dimgs[k].ntiles; ++t) tile_img[dimgs[k].tile0 + t] = k;
-
   rklt_plan* p = new (std::nothrow) rklt_plan;
   if (!p) return fail(RKLT_E_NOMEM, "rklt_plan_create: out of host memory");
   p->ctx = ctx;
   p->N = N;
-  p->block8 = b8;
   p->dump = dump;
   p->n = n;
-  p->total_tiles = total;
-  p->blocks_per_tile = blocks_per_tile;
-  p->blocks_per_thread = b8 ? bpt : 1;
-  p->wg = b8 ? wg : 256;
   p->pixels = pixels;
   hipError_t e = use_device(ctx->device);
   if (e != hipSuccess) {
     delete p;
     return hip_fail("hipSetDevice", e);
   }
-  if (grid_req > 0) {
-    p->grid = grid_req;
-  } else {
-    // enough workgroups to fill every CU several times over
-    const int per_cu = b8 ? (2048 / p->wg) : 8;
-    p->grid = ctx->cus * per_cu;
-  }
-  if (p->grid > total) p->grid = static_cast<int>(total);
-  e = hipMalloc(&p->d_imgs, sizeof(DevImage) * n);
-  if (e == hipSuccess) e = hipMalloc(&p->d_tile_img, sizeof(int32_t) * total);
-  if (e != hipSuccess) {
-    (void)hipFree(p->d_imgs);
-    delete p;
-    return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
-  }
-  e = hipMemcpy(p->d_imgs, dimgs.data(), sizeof(DevImage) * n, hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(p->d_tile_img, tile_img.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(p->d_imgs);
-    (void)hipFree(p->d_tile_img);
-    delete p;
-    return hip_fail("rklt_plan_create: hipMemcpy", e);
+  for (int c = 1; c >= 0; --c) {
+    if (by_class[c].empty()) continue;
+    st = build_part(ctx, by_class[c], c == 1, wg, bpt, grid_req, N, &p->parts[p->nparts]);
+    if (st) {
+      for (int k = 0; k < p->nparts; ++k) free_part(p->parts[k]);
+      delete p;
+      return st;
+    }
+    ++p->nparts;
   }
   *out = p;
   return RKLT_OK;
@@ -397,27 +487,29 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
 rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
   clear_error();
   if (!p || !d_res) return fail(RKLT_E_INVAL, "rklt_plan_run: NULL argument");
-  KArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.imgs = p->d_imgs;
-  a.tile_img = p->d_tile_img;
-  a.tf = p->ctx->d_table;
-  a.res = d_res;
-  a.total_tiles = static_cast<int32_t>(p->total_tiles);
-  a.blocks_per_tile = p->blocks_per_tile;
-  a.blocks_per_thread = p->blocks_per_thread;
-  a.dump = p->dump ? 1 : 0;
   hipError_t e = use_device(p->ctx->device);
   if (e != hipSuccess) return hip_fail("hipSetDevice", e);
-  return p->block8 ? launch_block8(a, p->grid, p->wg, stream) : launch_generic(p->N, a, p->grid, stream);
+  for (int k = 0; k < p->nparts; ++k) {
+    const PlanPart& q = p->parts[k];
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.imgs = q.d_imgs;
+    a.tile_img = q.d_tile_img;
+    a.tf = p->ctx->d_table;
+    a.res = d_res;
+    a.total_tiles = static_cast<int32_t>(q.total_tiles);
+    a.dump = p->dump ? 1 : 0;
+    const rklt_status st = q.block8 ? launch_block8(a, q.grid, q.wg, stream) : launch_generic(p->N, a, q.grid, stream);
+    if (st) return st;
+  }
+  return RKLT_OK;
 }
 
 rklt_status rklt_plan_destroy(rklt_plan* p) {
   clear_error();
   if (!p) return fail(RKLT_E_INVAL, "rklt_plan_destroy: plan is NULL");
   (void)use_device(p->ctx->device);
-  (void)hipFree(p->d_imgs);
-  (void)hipFree(p->d_tile_img);
+  for (int k = 0; k < p->nparts; ++k) free_part(p->parts[k]);
   delete p;
   return RKLT_OK;
 }
@@ -425,9 +517,37 @@ rklt_status rklt_plan_destroy(rklt_plan* p) {
 rklt_status rklt_plan_info(const rklt_plan* p, int64_t* tiles, int32_t* grid_wgs, int64_t* pixels) {
   clear_error();
   if (!p) return fail(RKLT_E_INVAL, "rklt_plan_info: plan is NULL");
-  if (tiles) *tiles = p->total_tiles;
-  if (grid_wgs) *grid_wgs = p->grid;
+  int64_t t = 0;
+  int32_t g = 0;
+  for (int k = 0; k < p->nparts; ++k) {
+    t += p->parts[k].total_tiles;
+    g += p->parts[k].grid;
+  }
+  if (tiles) *tiles = t;
+  if (grid_wgs) *grid_wgs = g;
   if (pixels) *pixels = p->pixels;
+  return RKLT_OK;
+}
+
+rklt_status rklt_plan_launches(const rklt_plan* p, int32_t* launches, int32_t* block8_images) {
+  clear_error();
+  if (!p) return fail(RKLT_E_INVAL, "rklt_plan_launches: plan is NULL");
+  int32_t b8 = 0;
+  for (int k = 0; k < p->nparts; ++k)
+    if (p->parts[k].block8) b8 += p->parts[k].n;
+  if (launches) *launches = p->nparts;
+  if (block8_images) *block8_images = b8;
+  return RKLT_OK;
+}
+
+rklt_status rklt_ctx_transform_exact(rklt_ctx* ctx, int32_t id, int32_t* exact, int64_t* den) {
+  clear_error();
+  if (!ctx) return fail(RKLT_E_INVAL, "rklt_ctx_transform_exact: ctx is NULL");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (id < 0 || id >= static_cast<int>(ctx->host.size()))
+    return fail(RKLT_E_INVAL, "rklt_ctx_transform_exact: unknown transform id %d", id);
+  if (exact) *exact = ctx->host[id].exact;
+  if (den) *den = ctx->host[id].den;
   return RKLT_OK;
 }
 

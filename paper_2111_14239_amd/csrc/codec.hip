@@ -68,28 +68,30 @@ __device__ __forceinline__ int dot2(int a, int b, int acc) {
                                 false);
 }
 
-// floor, clip to [0, 255] and place as byte `k` of `word`.
-__device__ __forceinline__ uint32_t pack_pixel(float x, int k, uint32_t word) {
-  const float v = __builtin_amdgcn_fmed3f(floorf(x), 0.0f, 255.0f);
-  return __builtin_amdgcn_cvt_pk_u8_f32(v, k, word);
-}
-
 // Code one 8 x 8 block with level shift 128.  s/d point at its top-left
 // pixel; sxx accumulates sum(x^2) + sum(y^2) and sxy sum(x y) over the
 // original x and the reconstruction y.
 //
 // The scaling and the inverse merge: T_hat^-1 = T^-1 S^-1, so
 //   T_hat^-1 (mask (.) (s s^T) (.) B) T_hat^-T = T^-1 (mask (.) B) T^-T,
-// and both inverse stages take T^-1 directly (the scaled coefficients
-// s_i s_j B_ij are written only by the verification dump).
+// and with T^-1 = adj / den (integer adj) the reconstruction is
+//   A' - 128 = Out / den^2,   Out = adj (mask (.) B) adj^T.
+// Both inverse stages run as FP32 FMAs on integer values; the host checked
+// that every product and partial sum stays below 2^24 in magnitude, so each
+// FMA is exact and Out is the exact integer.  The scaled coefficients
+// s_i s_j B_ij are written only by the verification dump.  Pixels are
+// floor(Out / den^2 + 1/2) + 128, clipped: Out * inv_den2 + (128 + delta)
+// lies within 4e-5 of the exact value plus delta, half the 1/den^2 spacing
+// of the rationals away from every rounding boundary, so the saturating
+// round-to-nearest byte conversion returns the exact result, ties included.
 //
 // Loop order keeps few table words live: rows i of B outer in the forward
-// column stage (one row of T and one column of T^-1 at a time), output
-// columns n outer in the last inverse stage (one row of T^-1 at a time).
+// column stage (one row of T and one column of adj at a time), output
+// columns n outer in the last inverse stage (one row of adj at a time).
 template <int D, bool DUMP>
 __device__ __forceinline__ void block8(const uint8_t* __restrict__ s, int ps, uint8_t* __restrict__ d,
                                        int pd, const DevTransform* __restrict__ table, int tid, int r,
-                                       float base, int32_t* __restrict__ coef, float* __restrict__ scaled,
+                                       int32_t* __restrict__ coef, float* __restrict__ scaled,
                                        uint32_t& sxx, uint32_t& sxy) {
   constexpr int C = D < 8 ? D : 8;  // columns j (and rows i) that hold a kept coefficient
   // Opaque transform index: the table is read from the scalar cache where it
@@ -122,8 +124,8 @@ __device__ __forceinline__ void block8(const uint8_t* __restrict__ s, int ps, ui
   }
 
   // Columns and first inverse stage:
-  //   B[i][j] = sum_m T[i][m] Y[m][j]                         (int16 dots)
-  //   W[m][j] = sum_{i : (i, j) kept} Ti[m][i] B[i][j]        (FP32, Ti = T^-1)
+  //   B[i][j] = sum_m T[i][m] Y[m][j]                      (int16 dots)
+  //   W[m][j] = sum_{i : (i, j) kept} adj[m][i] B[i][j]    (exact FP32)
   float W[8][C];
 #pragma unroll
   for (int i = 0; i < C; ++i) {
@@ -138,24 +140,29 @@ __device__ __forceinline__ void block8(const uint8_t* __restrict__ s, int ps, ui
         if (scaled) as_global(scaled)[i * 8 + j] = static_cast<float>(B) * tf->w[i * 8 + j];
       }
       float c = static_cast<float>(B);
-      // the last anti-diagonal is kept only up to zig-zag position r - 1
-      if (i + j == D - 1 && zz_rank(8, i, j) >= r) c = 0.0f;
+      // Zonal mask.  With D from r, every position on the anti-diagonals
+      // before D - 1 has zig-zag rank < r, so only the last one is tested;
+      // the dump computes all 64 coefficients and tests every position.
+      if ((DUMP || i + j == D - 1) && zz_rank(8, i, j) >= r) c = 0.0f;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) W[m][j] = (i == 0) ? tf->Ti[m * 8 + i] * c : fmaf(tf->Ti[m * 8 + i], c, W[m][j]);
+      for (int m = 0; m < 8; ++m)
+        W[m][j] = (i == 0) ? tf->fadj[m * 8 + i] * c : fmaf(tf->fadj[m * 8 + i], c, W[m][j]);
     }
   }
 
   // Second inverse stage, output column n outer:
-  //   A[m][n] = 128 + 1/2 + sum_j W[m][j] Ti[n][j]
+  //   Out[m][n] = sum_j W[m][j] adj[n][j];  pixel = RNE(Out * inv_den2 + bias)
+  const float inv = tf->inv_den2, bias = tf->bias;
   uint32_t out[8][2];
 #pragma unroll
   for (int n = 0; n < 8; ++n) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      float acc = base;
+      float acc = W[m][0] * tf->fadj[n * 8 + 0];
 #pragma unroll
-      for (int j = 0; j < C; ++j) acc = fmaf(W[m][j], tf->Ti[n * 8 + j], acc);
-      out[m][n >> 2] = pack_pixel(acc, n & 3, (n & 3) ? out[m][n >> 2] : 0u);
+      for (int j = 1; j < C; ++j) acc = fmaf(W[m][j], tf->fadj[n * 8 + j], acc);
+      const float y = fmaf(acc, inv, bias);
+      out[m][n >> 2] = __builtin_amdgcn_cvt_pk_u8_f32(y, n & 3, (n & 3) ? out[m][n >> 2] : 0u);
     }
   }
 #pragma unroll
@@ -184,15 +191,20 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
 
 // Add one tile's squared error to its image and finalise the image when this
 // was its last tile.  Called by one thread.
+//
+// res->acc packs the tile count above bit 48 and the running SSE below it
+// (SSE < 2^31 pixels * 255^2 < 2^48; the host keeps an image's tiles below
+// 2^16).  One relaxed atomic add per tile returns the previous value, so the
+// tile that brings the count to ntiles holds the whole sum in its own result:
+// no fence and no second read are needed, and no L2 write-back is forced
+// while other workgroups still stream pixels through it.
 __device__ void finish_tile(rklt_result* res, unsigned long long sum, int ntiles, long long npix) {
   unsigned long long* acc = reinterpret_cast<unsigned long long*>(&res->acc);
-  atomicAdd(acc, sum);
-  __threadfence();
-  const unsigned prev = atomicAdd(&res->done, 1u);
-  if (prev + 1u == static_cast<unsigned>(ntiles)) {
-    __threadfence();
-    const unsigned long long sse = atomicExch(acc, 0ull);
-    atomicExch(&res->done, 0u);
+  const unsigned long long mine = sum + (1ull << 48);
+  const unsigned long long now = atomicAdd(acc, mine) + mine;
+  if ((now >> 48) == static_cast<unsigned long long>(ntiles)) {
+    const unsigned long long sse = now & ((1ull << 48) - 1);
+    atomicExch(acc, 0ull);
     const float mse = static_cast<float>(sse) / static_cast<float>(npix);
     res->sse = sse;
     res->mse = mse;
@@ -218,36 +230,39 @@ __device__ __forceinline__ void reduce_and_finish(unsigned long long mine, unsig
 
 template <bool DUMP>
 __device__ __forceinline__ void block8_dispatch(int D, const uint8_t* s, int ps, uint8_t* d, int pd,
-                                                const DevTransform* table, int tid, int r, float base,
+                                                const DevTransform* table, int tid, int r,
                                                 int32_t* coef, float* scaled, uint32_t& sxx,
                                                 uint32_t& sxy) {
 #define RKLT_CASE(DD) \
   case DD:            \
-    block8<DD, DUMP>(s, ps, d, pd, table, tid, r, base, coef, scaled, sxx, sxy); \
+    block8<DD, DUMP>(s, ps, d, pd, table, tid, r, coef, scaled, sxx, sxy); \
     break;
   switch (D) {
     RKLT_CASE(1) RKLT_CASE(2) RKLT_CASE(3) RKLT_CASE(4) RKLT_CASE(5) RKLT_CASE(6) RKLT_CASE(7)
     RKLT_CASE(8) RKLT_CASE(9) RKLT_CASE(10) RKLT_CASE(11) RKLT_CASE(12) RKLT_CASE(13)
     RKLT_CASE(14)
     default:
-      block8<15, DUMP>(s, ps, d, pd, table, tid, r, base, coef, scaled, sxx, sxy);
+      block8<15, DUMP>(s, ps, d, pd, table, tid, r, coef, scaled, sxx, sxy);
       break;
   }
 #undef RKLT_CASE
 }
 
+// PLAN: a batch plan's work list (persistent grid); otherwise the plain
+// path's single image from the kernel argument, one tile per workgroup.
+template <bool PLAN>
 __global__ __launch_bounds__(256) void rklt_block8_kernel(KArgs a) {
   __shared__ unsigned long long red[4];
   for (int tile = blockIdx.x; tile < a.total_tiles; tile += gridDim.x) {
-    const int ii = a.imgs ? __builtin_amdgcn_readfirstlane(a.tile_img[tile]) : 0;
-    const DevImage* im = a.imgs ? a.imgs + ii : &a.one;
+    const int ii = PLAN ? __builtin_amdgcn_readfirstlane(a.tile_img[tile]) : 0;
+    const DevImage* im = PLAN ? a.imgs + ii : &a.one;
     const int tid = __builtin_amdgcn_readfirstlane(im->tid);
-    const int b0 = (tile - im->tile0) * a.blocks_per_tile;
+    const int tile_blocks = im->tile_blocks;
+    const int b0 = (tile - im->tile0) * tile_blocks;
     const int nblocks = im->nblocks, bw = im->bw, ps = im->ps, pd = im->pd;
     const int r = im->r, D = a.dump ? 15 : im->D;
-    const float base = 128.5f;
     uint32_t sxx = 0, sxy = 0;
-    for (int k = 0; k < a.blocks_per_thread; ++k) {
+    for (int k = 0; k * static_cast<int>(blockDim.x) < tile_blocks; ++k) {
       const int b = b0 + k * static_cast<int>(blockDim.x) + static_cast<int>(threadIdx.x);
       if (b < nblocks) {
         const int by = b / bw, bx = b - by * bw;
@@ -256,14 +271,14 @@ __global__ __launch_bounds__(256) void rklt_block8_kernel(KArgs a) {
         if (a.dump) {
           int32_t* coef = im->coef ? im->coef + static_cast<size_t>(b) * 64 : nullptr;
           float* scaled = im->scaled ? im->scaled + static_cast<size_t>(b) * 64 : nullptr;
-          block8<15, true>(s, ps, d, pd, a.tf, tid, r, base, coef, scaled, sxx, sxy);
+          block8<15, true>(s, ps, d, pd, a.tf, tid, r, coef, scaled, sxx, sxy);
         } else {
-          block8_dispatch<false>(D, s, ps, d, pd, a.tf, tid, r, base, nullptr, nullptr, sxx, sxy);
+          block8_dispatch<false>(D, s, ps, d, pd, a.tf, tid, r, nullptr, nullptr, sxx, sxy);
         }
       }
     }
     const uint32_t mine = sxx - 2u * sxy;
-    reduce_and_finish(mine, red, a.res + ii, im->ntiles, static_cast<long long>(im->H) * im->W);
+    reduce_and_finish(mine, red, a.res + im->slot, im->ntiles, static_cast<long long>(im->H) * im->W);
   }
 }
 
@@ -278,7 +293,7 @@ struct GenericShape {
   static constexpr int TILE_BLOCKS = 4096 / NN;  // 4096 pixels per tile
 };
 
-template <int N>
+template <int N, bool PLAN>
 __global__ __launch_bounds__(256) void rklt_generic_kernel(KArgs a) {
   using S = GenericShape<N>;
   constexpr int NN = S::NN, BPI = S::BPI, PPT = S::PPT, ITEMS = S::ITEMS;
@@ -293,8 +308,8 @@ __global__ __launch_bounds__(256) void rklt_generic_kernel(KArgs a) {
   __shared__ unsigned long long red[4];
   int loaded = -1;
   for (int tile = blockIdx.x; tile < a.total_tiles; tile += gridDim.x) {
-    const int ii = a.imgs ? a.tile_img[tile] : 0;
-    const DevImage* im = a.imgs ? a.imgs + ii : &a.one;
+    const int ii = PLAN ? a.tile_img[tile] : 0;
+    const DevImage* im = PLAN ? a.imgs + ii : &a.one;
     const DevTransform* tf = a.tf + im->tid;
     if (im->tid != loaded) {
       __syncthreads();
@@ -307,11 +322,12 @@ __global__ __launch_bounds__(256) void rklt_generic_kernel(KArgs a) {
       __syncthreads();
       loaded = im->tid;
     }
-    const int b0 = (tile - im->tile0) * a.blocks_per_tile;
+    const int tile_blocks = im->tile_blocks;
+    const int b0 = (tile - im->tile0) * tile_blocks;
     const int nblocks = im->nblocks, bw = im->bw, r = im->r, ell = im->ell;
     const float base = static_cast<float>(ell) + 0.5f;
     unsigned long long sse = 0;
-    for (int it = 0; it * BPI < a.blocks_per_tile; ++it) {
+    for (int it = 0; it * BPI < tile_blocks; ++it) {
       const int bbase = b0 + it * BPI;
       if (bbase >= nblocks) break;
       int orig[PPT];
@@ -389,7 +405,7 @@ __global__ __launch_bounds__(256) void rklt_generic_kernel(KArgs a) {
       }
       __syncthreads();
     }
-    reduce_and_finish(sse, red, a.res + ii, im->ntiles, static_cast<long long>(im->H) * im->W);
+    reduce_and_finish(sse, red, a.res + im->slot, im->ntiles, static_cast<long long>(im->H) * im->W);
   }
 }
 
@@ -407,6 +423,16 @@ rklt_status launched(const char* what) {
 
 }  // namespace
 
+int generic_blocks_per_iteration(int N) {
+  switch (N) {
+    case 4: return GenericShape<4>::BPI;
+    case 8: return GenericShape<8>::BPI;
+    case 16: return GenericShape<16>::BPI;
+    case 32: return GenericShape<32>::BPI;
+    default: return 0;
+  }
+}
+
 int generic_blocks_per_tile(int N) {
   switch (N) {
     case 4: return GenericShape<4>::TILE_BLOCKS;
@@ -418,17 +444,25 @@ int generic_blocks_per_tile(int N) {
 }
 
 rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream) {
-  hipLaunchKernelGGL(rklt_block8_kernel, dim3(grid), dim3(wg), 0, static_cast<hipStream_t>(stream), a);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (a.imgs) hipLaunchKernelGGL(rklt_block8_kernel<true>, dim3(grid), dim3(wg), 0, st, a);
+  else hipLaunchKernelGGL(rklt_block8_kernel<false>, dim3(grid), dim3(wg), 0, st, a);
   return launched("rklt_block8_kernel");
+}
+
+template <int N>
+void launch_generic_n(const KArgs& a, int grid, hipStream_t st) {
+  if (a.imgs) hipLaunchKernelGGL((rklt_generic_kernel<N, true>), dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((rklt_generic_kernel<N, false>), dim3(grid), dim3(256), 0, st, a);
 }
 
 rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream) {
   const hipStream_t st = static_cast<hipStream_t>(stream);
   switch (N) {
-    case 4: hipLaunchKernelGGL(rklt_generic_kernel<4>, dim3(grid), dim3(256), 0, st, a); break;
-    case 8: hipLaunchKernelGGL(rklt_generic_kernel<8>, dim3(grid), dim3(256), 0, st, a); break;
-    case 16: hipLaunchKernelGGL(rklt_generic_kernel<16>, dim3(grid), dim3(256), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(rklt_generic_kernel<32>, dim3(grid), dim3(256), 0, st, a); break;
+    case 4: launch_generic_n<4>(a, grid, st); break;
+    case 8: launch_generic_n<8>(a, grid, st); break;
+    case 16: launch_generic_n<16>(a, grid, st); break;
+    case 32: launch_generic_n<32>(a, grid, st); break;
     default: return fail(RKLT_E_INVAL, "generic kernel: N=%d not supported", N);
   }
   return launched("rklt_generic_kernel");

@@ -15,6 +15,9 @@ void clear_error();
 
 rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out);
 rklt_status zigzag(int N, int32_t* order);
+// Exact inverse of an integer matrix with entries in [-8, 8], N <= 8:
+// T^-1 = adj / den in lowest terms, den > 0.  False if singular or out of range.
+bool exact_inverse(int N, const int32_t* T, int64_t* adj, int64_t* den);
 
 constexpr int kMaxTransforms = 256;
 
@@ -25,6 +28,18 @@ struct alignas(256) DevTransform {
   int32_t sig[RKLT_MAX_N];       // sigma_i = sum_j T_ij (row sums)
   int32_t t8[8][2];              // N = 8: row j of T as int8x4 words, n = 0..3 | 4..7
   int32_t t16[8][4];             // N = 8: row i of T as int16x2 words, (m, m+1) pairs
+  // N = 8 inverse constants.  The register kernel reconstructs
+  //   pixel = RNE_sat(Out * inv_den2 + bias),  Out = fadj (mask (.) B) fadj^T.
+  // exact = 1: T^-1 = adj / den with integer adj, fadj = adj, inv_den2 =
+  //   1/den^2, bias = 128 + delta; every FMA is exact and the pixel equals
+  //   floor(Out / den^2 + 1/2) + 128 exactly (bounds checked on the host).
+  // exact = 0: fadj = T^-1 in FP32, inv_den2 = 1, bias = 128 + 2^-12 (an FP32
+  //   reconstruction; exact ties go up as floor(x + 1/2) does).
+  int32_t exact;
+  int32_t den;
+  float inv_den2, bias;
+  int32_t adj[64];
+  float fadj[64];                // m*8 + i
   float w[RKLT_MAX_N * RKLT_MAX_N];     // s_i s_j at i*N + j
   float G[RKLT_MAX_N * RKLT_MAX_N];     // T_hat^-1 at m*N + i
   float Ti[RKLT_MAX_N * RKLT_MAX_N];    // T^-1 = T_hat^-1 S at m*N + i
@@ -42,6 +57,9 @@ struct DevImage {
   int32_t H, W, ps, pd;
   int32_t tid, r, ell, D;  // D: anti-diagonals i + j < D hold every kept coefficient
   int32_t bw, nblocks, tile0, ntiles;
+  int32_t slot;            // index of this image's rklt_result
+  int32_t tile_blocks;     // blocks per tile (the image has ntiles <= 65535 tiles)
+  int32_t pad[2];
 };
 
 struct KArgs {
@@ -50,8 +68,6 @@ struct KArgs {
   const DevTransform* tf;    // context transform table
   rklt_result* res;          // one per image
   int32_t total_tiles;
-  int32_t blocks_per_tile;
-  int32_t blocks_per_thread;  // N = 8 path
   int32_t dump;               // write coefficient dumps
   DevImage one;               // the image of the plain path
 };
@@ -72,5 +88,7 @@ rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream);
 rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream);
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
 int generic_blocks_per_tile(int N);
+int generic_blocks_per_iteration(int N);
+constexpr int kMaxTilesPerImage = 65535;  // tile count field of the packed accumulator
 
 }  // namespace rklt

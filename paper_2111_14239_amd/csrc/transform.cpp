@@ -177,6 +177,66 @@ rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out
   return RKLT_OK;
 }
 
+bool exact_inverse(int N, const int32_t* T, int64_t* adj, int64_t* den) {
+  // Fraction-free Gauss-Jordan elimination of [T | I] over the integers: each
+  // update (p_k M_ij - M_ik M_kj) / p_{k-1} divides exactly, the left block
+  // ends as D I with D = +-det T and the right block as the matching
+  // adjugate, so T^-1 = right / D.  The result is reduced to lowest terms
+  // and checked (T adj = den I) before it is returned.
+  typedef __int128 i128;
+  if (N < 1 || N > 8) return false;
+  i128 M[8][16];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      if (T[i * N + j] > 8 || T[i * N + j] < -8) return false;  // keeps every product in range
+      M[i][j] = T[i * N + j];
+      M[i][N + j] = (i == j) ? 1 : 0;
+    }
+  i128 prev = 1;
+  for (int k = 0; k < N; ++k) {
+    int p = k;
+    while (p < N && M[p][k] == 0) ++p;
+    if (p == N) return false;
+    if (p != k)
+      for (int j = 0; j < 2 * N; ++j) std::swap(M[p][j], M[k][j]);
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      const i128 f = M[i][k];
+      for (int j = 0; j < 2 * N; ++j) {
+        const i128 num = M[k][k] * M[i][j] - f * M[k][j];
+        if (num % prev != 0) return false;
+        M[i][j] = num / prev;
+      }
+    }
+    prev = M[k][k];
+  }
+  i128 D = M[N - 1][N - 1];
+  for (int i = 0; i < N; ++i)
+    if (M[i][i] != D) return false;
+  i128 g = D < 0 ? -D : D;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      i128 a = M[i][N + j] < 0 ? -M[i][N + j] : M[i][N + j];
+      while (a != 0) {
+        const i128 t = g % a;
+        g = a;
+        a = t;
+      }
+    }
+  if (g == 0) return false;
+  const int sign = D < 0 ? -1 : 1;
+  *den = static_cast<int64_t>(sign * D / g);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) adj[i * N + j] = static_cast<int64_t>(sign * M[i][N + j] / g);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      i128 acc = 0;
+      for (int k = 0; k < N; ++k) acc += static_cast<i128>(T[i * N + k]) * adj[k * N + j];
+      if (acc != ((i == j) ? static_cast<i128>(*den) : 0)) return false;
+    }
+  return true;
+}
+
 rklt_status zigzag(int N, int32_t* order) {
   if (!order) return fail(RKLT_E_INVAL, "rklt_zigzag: order is NULL");
   if (N < 1 || N > RKLT_MAX_N) return fail(RKLT_E_INVAL, "rklt_zigzag: N=%d outside 1..%d", N, RKLT_MAX_N);

@@ -53,7 +53,7 @@ class Image(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("sse", C.c_uint64), ("mse", C.c_float), ("psnr_db", C.c_float),
-                ("acc", C.c_uint64), ("done", C.c_uint32), ("tiles", C.c_uint32)]
+                ("acc", C.c_uint64), ("tiles", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 RESULT_BYTES = C.sizeof(Result)  # 32
@@ -88,6 +88,8 @@ def _load():
         "rklt_plan_destroy": (st, [vp]),
         "rklt_plan_info": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_copy_bytes": (st, [vp, vp, C.c_size_t, vp]),
+        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -99,7 +101,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_create",
             "rklt_ctx_destroy", "rklt_ctx_add_transform", "rklt_codec", "rklt_plan_create",
-            "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes")
+            "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
+            "rklt_plan_launches", "rklt_ctx_transform_exact")
 
 
 def lib():
@@ -194,7 +197,7 @@ def read_results(res_tensor) -> list[dict]:
     n = len(raw) // RESULT_BYTES
     arr = (Result * n).from_buffer_copy(raw)
     return [dict(sse=int(r.sse), mse=float(r.mse), psnr_db=float(r.psnr_db), tiles=int(r.tiles),
-                 acc=int(r.acc), done=int(r.done)) for r in arr]
+                 acc=int(r.acc)) for r in arr]
 
 
 def image_desc(src, transform_id: int, r: int, dst=None, level_shift: int = 128,
@@ -246,6 +249,12 @@ class Context:
             self._ids[key] = self.add_transform(build_transform(N, rho, alpha))
         return self._ids[key]
 
+    def transform_exact(self, tid: int) -> tuple[bool, int]:
+        """(exact, den): whether the N = 8 register kernel reconstructs exactly."""
+        e, d = C.c_int32(), C.c_int64()
+        _check(_lib.rklt_ctx_transform_exact(self._h, int(tid), C.byref(e), C.byref(d)))
+        return bool(e.value), int(d.value)
+
     def codec(self, img: Image, res_ptr: int, tuning: Tuning | None = None, stream=None):
         """rklt_codec: one image, one launch (plain path)."""
         _check(_lib.rklt_codec(self._h, C.byref(img), C.c_void_p(res_ptr),
@@ -270,6 +279,9 @@ class Plan:
         tiles, grid, pixels = C.c_int64(), C.c_int32(), C.c_int64()
         _check(_lib.rklt_plan_info(h, C.byref(tiles), C.byref(grid), C.byref(pixels)))
         self.tiles, self.grid, self.pixels = int(tiles.value), int(grid.value), int(pixels.value)
+        nl, nb8 = C.c_int32(), C.c_int32()
+        _check(_lib.rklt_plan_launches(h, C.byref(nl), C.byref(nb8)))
+        self.launches, self.block8_images = int(nl.value), int(nb8.value)
 
     def run(self, res_ptr: int, stream=None):
         _check(_lib.rklt_plan_run(self._h, C.c_void_p(res_ptr), C.c_void_p(_stream_handle(stream))))
