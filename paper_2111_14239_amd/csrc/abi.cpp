@@ -358,6 +358,12 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
   int wg, bpt, grid_req;
   rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
   if (st) return st;
+  if (!tuning) {
+    // One image per launch: small tiles, so that even a 1-megapixel image
+    // spreads over every CU.
+    wg = 64;
+    bpt = 1;
+  }
   KArgs a;
   std::memset(&a, 0, sizeof(a));
   int N = 0;
