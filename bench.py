@@ -34,7 +34,7 @@ from paper_2111_14239_amd.inputs import fixed_batch  # noqa: E402
 METRIC = "Mpixel/s fwd+zonal+inv+PSNR (batched vs plain), % HBM peak, p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PIXEL = 2  # read the uint8 pixel, write the uint8 reconstruction
-KERNEL = "rklt_block8_kernel"
+KERNEL = "rklt_mfma8_kernel"
 CPU_SAMPLE_IMAGES = 64
 CPU_SECONDS = 12.0
 
@@ -221,7 +221,8 @@ def main():
                         "level shift 128, one persistent launch per step",
             "images": n, "rejected_alpha1": rejected, "pixels": pixels,
             "tiles": plan.tiles, "grid_wgs": plan.grid, "launches_per_step": plan.launches,
-            "register_kernel_images": plan.block8_images,
+            "images_per_kernel_class": dict(zip(("generic", "register_n8", "matrix_core_n8"),
+                                                plan.images_per_class)),
             "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 4,
         },
         "roofline": {

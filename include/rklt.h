@@ -185,11 +185,16 @@ rklt_status rklt_plan_destroy(rklt_plan* plan);
 /* Number of tiles and of workgroups the plan launches (for reporting). */
 rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_wgs,
                            int64_t* pixels);
-/* A plan launches one kernel per kernel class among its images: the N = 8
- * register kernel (level shift 128, |T_ij| <= 127, 128 * max row L1 <= 32767)
- * and the generic LDS kernel (everything else).  Reports the number of
- * launches per run and how many images take the register kernel. */
-rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* block8_images);
+/* A plan launches one kernel per kernel class among its images:
+ *   class 2  the N = 8 matrix-core kernel: level shift 128 and a transform
+ *            whose exact inverse fits its operands (every {0, +-1} T of
+ *            alpha in {2, 3} but one);
+ *   class 1  the N = 8 register kernel: level shift 128, |T_ij| <= 127,
+ *            128 * max row L1 <= 32767 (also every plan that dumps coefficients);
+ *   class 0  the generic LDS kernel: everything else.
+ * Reports the number of launches per run and, in images_per_class[3] (may be
+ * NULL), how many images each class codes. */
+rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* images_per_class);
 
 /* ---- measurement -------------------------------------------------------- */
 

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librklt.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["codec.hip", "abi.cpp", "transform.cpp"]
+SOURCES = ["codec.hip", "codec_mfma.hip", "abi.cpp", "transform.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -42,25 +42,28 @@ def _run(cmd):
     return err
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link librklt.so; returns the library path."""
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines: tuple = ()) -> str:
+    """Compile every source and link librklt.so (or `out`, with extra -D
+    `defines`, for tuning experiments); returns the library path."""
+    objdir = OBJDIR if out == LIB else out + ".objs"
+    os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
     jobs = []
     for src in SOURCES:
-        obj = os.path.join(OBJDIR, src.rsplit(".", 1)[0] + ".o")
+        obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"]
-        jobs.append(([hipcc, *lang, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+        defs = [f"-D{d}" for d in defines]
+        jobs.append(([hipcc, *lang, *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         outs = list(ex.map(lambda j: _run(j[0]), jobs))
     if verbose:
         for o in outs:
             if o:
                 print(o, file=sys.stderr)
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for _, o in jobs]])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

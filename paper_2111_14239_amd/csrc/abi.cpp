@@ -23,7 +23,7 @@ struct rklt_ctx {
 
 // One launch of a plan: the images of one kernel class.
 struct PlanPart {
-  bool block8 = false;
+  int cls = 0;  // kernel class (see kernel_class)
   int n = 0;
   rklt::DevImage* d_imgs = nullptr;
   int32_t* d_tile_img = nullptr;
@@ -38,7 +38,7 @@ struct rklt_plan {
   bool dump = false;
   int n = 0;
   int nparts = 0;
-  PlanPart parts[2];
+  PlanPart parts[3];
   int64_t pixels = 0;
 };
 
@@ -50,10 +50,20 @@ thread_local char g_error[512] = "";
 constexpr int kDefaultWg = 256;
 constexpr int kDefaultBpt = 4;
 
+// Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
+// 0 = generic LDS kernel.  Coefficient dumps are written by the register and
+// generic kernels.
+int kernel_class(const DevTransform& t, int ell, bool dump);
+
 bool block8_fits(const DevTransform& t, int ell) {
   // level shift 128 (pixel xor 0x80), int8 entries for the row dots and
   // |Y| <= 128 * L1 within int16 for the column dots
   return ell == 128 && t.N == 8 && t.max_abs <= 127 && 128 * t.max_row_l1 <= 32767;
+}
+
+int kernel_class(const DevTransform& t, int ell, bool dump) {
+  if (!block8_fits(t, ell)) return 0;
+  return (t.mfma && !dump) ? 2 : 1;
 }
 
 hipError_t use_device(int device) {
@@ -310,6 +320,65 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
       }
     }
   }
+  if (N == 8 && dt.exact) {
+    // Matrix-core operands.  Exactness needs: forward weights T_im T_jn in
+    // int8; |B| <= 32768 so that B = hi + lo with hi = fp16(B) and |lo| <= 8,
+    // both exact in fp16; inverse weights adj_mi adj_nj exact fp16 integers
+    // (|.| <= 2048); and every partial sum of the inverse below 2^24, bounded
+    // by sum_ij |adj_mi adj_nj| (Bmax_ij + 16).
+    int32_t order[64];
+    zigzag(8, order);
+    double L1[8];
+    for (int i = 0; i < 8; ++i) {
+      L1[i] = 0;
+      for (int j = 0; j < 8; ++j) L1[i] += std::abs(t->T[i * 8 + j]);
+    }
+    bool ok = max_abs * max_abs <= 127;
+    double omax = 0;
+    for (int m = 0; m < 8 && ok; ++m)
+      for (int n = 0; n < 8 && ok; ++n) {
+        double o = 0;
+        for (int i = 0; i < 8; ++i)
+          for (int j = 0; j < 8; ++j) {
+            const double w = std::fabs(static_cast<double>(dt.adj[m * 8 + i]) * dt.adj[n * 8 + j]);
+            const double bmax = 128.0 * L1[i] * L1[j];
+            if (w > 2048.0 || bmax > 32768.0) ok = false;
+            o += w * (bmax + 16.0);
+          }
+        omax = std::fmax(omax, o);
+      }
+    if (ok && omax < 16777216.0) {
+      dt.mfma = 1;
+      for (int mu = 0; mu < 2; ++mu)
+        for (int c = 0; c < 2; ++c)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int o = order[32 * mu + (lane & 31)];
+            const int i = o / 8, j = o % 8;
+            for (int w = 0; w < 4; ++w) {
+              uint32_t word = 0;
+              for (int b = 0; b < 4; ++b) {
+                const int e = 4 * w + b;
+                const int row = 4 * c + 2 * (lane >> 5) + e / 8, col = e % 8;
+                const int v = t->T[i * 8 + row] * t->T[j * 8 + col];
+                word |= (static_cast<uint32_t>(v) & 0xffu) << (8 * b);
+              }
+              dt.mF[mu][c][lane][w] = static_cast<int32_t>(word);
+            }
+          }
+      for (int mu = 0; mu < 2; ++mu)
+        for (int kappa = 0; kappa < 8; ++kappa)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int M = lane & 31;
+            const int g = M >> 3, hm = (M >> 2) & 1, v = M & 3;
+            const int m = 4 * mu + 2 * hm + g / 2, n = 4 * (g % 2) + v;
+            for (int e = 0; e < 8; ++e) {
+              const int o = order[8 * kappa + 4 * (lane >> 5) + e / 2];
+              const int i = o / 8, j = o % 8;
+              dt.mV[mu][kappa][lane][e] = static_cast<_Float16>(static_cast<float>(dt.adj[m * 8 + i] * dt.adj[n * 8 + j]));
+            }
+          }
+    }
+  }
   if (N == 8 && !dt.exact) {
     dt.den = 0;
     dt.inv_den2 = 1.0f;
@@ -371,11 +440,12 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     std::lock_guard<std::mutex> lock(ctx->mu);
     if ((st = check_image(ctx, *img, 0, &a.one, &N))) return st;
     a.dump = (img->coef_out || img->scaled_out) ? 1 : 0;
-    const bool b8 = block8_fits(ctx->host[img->transform_id], img->level_shift);
+    const int cls = kernel_class(ctx->host[img->transform_id], img->level_shift, a.dump != 0);
     a.one.tile0 = 0;
     a.one.slot = 0;
-    a.one.tile_blocks = b8 ? image_tile_blocks(a.one, wg * bpt, wg)
-                           : image_tile_blocks(a.one, generic_blocks_per_tile(N), generic_blocks_per_iteration(N));
+    a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
+                        : cls == 1 ? image_tile_blocks(a.one, wg * bpt, wg)
+                                   : image_tile_blocks(a.one, generic_blocks_per_tile(N), generic_blocks_per_iteration(N));
     a.one.ntiles = (a.one.nblocks + a.one.tile_blocks - 1) / a.one.tile_blocks;
     a.total_tiles = a.one.ntiles;
     a.tf = ctx->d_table;
@@ -383,7 +453,9 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     hipError_t e = use_device(ctx->device);
     if (e != hipSuccess) return hip_fail("hipSetDevice", e);
     const int grid = a.total_tiles;
-    return b8 ? launch_block8(a, grid, wg, stream) : launch_generic(N, a, grid, stream);
+    return cls == 2 ? launch_mfma8(a, grid, wg, stream)
+           : cls == 1 ? launch_block8(a, grid, wg, stream)
+                      : launch_generic(N, a, grid, stream);
   }
 }
 
@@ -397,10 +469,11 @@ void free_part(PlanPart& q) {
 }
 
 // Tile the images of one kernel class and upload the work list.
-rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, bool b8, int wg, int bpt, int grid_req, int N,
+rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int N,
                        PlanPart* q) {
-  const int base = b8 ? wg * bpt : generic_blocks_per_tile(N);
-  const int unit = b8 ? wg : generic_blocks_per_iteration(N);
+  const bool b8 = cls > 0;
+  const int base = cls == 2 ? (wg / 2) * bpt : b8 ? wg * bpt : generic_blocks_per_tile(N);
+  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : generic_blocks_per_iteration(N);
   int64_t total = 0;
   for (auto& d : imgs) {
     d.tile0 = static_cast<int32_t>(total);
@@ -412,12 +485,19 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, bool b8, int 
   std::vector<int32_t> tile_img(static_cast<size_t>(total));
   for (size_t k = 0; k < imgs.size(); ++k)
     for (int t = 0; t < imgs[k].ntiles; ++t) tile_img[imgs[k].tile0 + t] = static_cast<int32_t>(k);
-  q->block8 = b8;
+  q->cls = cls;
   q->n = static_cast<int>(imgs.size());
   q->total_tiles = total;
   q->wg = b8 ? wg : 256;
-  // enough workgroups to fill every CU several times over
-  q->grid = grid_req > 0 ? grid_req : ctx->cus * (b8 ? 2048 / q->wg : 8);
+  // The matrix-core kernel schedules statically over a resident grid (one
+  // workgroup per resident slot); the others take enough workgroups to fill
+  // every CU several times over.
+  int auto_grid = ctx->cus * (b8 ? 2048 / q->wg : 8);
+  if (cls == 2) {
+    const int per_cu = mfma8_resident_wgs_per_cu(q->wg);
+    if (per_cu > 0) auto_grid = ctx->cus * per_cu;
+  }
+  q->grid = grid_req > 0 ? grid_req : auto_grid;
   if (q->grid > total) q->grid = static_cast<int>(total);
   hipError_t e = hipMalloc(&q->d_imgs, sizeof(DevImage) * imgs.size());
   if (e == hipSuccess) e = hipMalloc(&q->d_tile_img, sizeof(int32_t) * total);
@@ -444,7 +524,8 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
   int wg, bpt, grid_req;
   rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
   if (st) return st;
-  std::vector<DevImage> by_class[2];  // [0] generic kernel, [1] N = 8 register kernel
+  std::vector<DevImage> by_class[3];  // indexed by kernel class
+  std::vector<DevImage> dimgs_all;
   int N = 0;
   bool dump = false;
   int64_t pixels = 0;
@@ -458,11 +539,13 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
       else if (Nk != N)
         return fail(RKLT_E_INVAL, "image %d: N=%d differs from N=%d of image 0 (one N per plan)", k, Nk, N);
       d.slot = k;
-      const bool b8 = block8_fits(ctx->host[imgs[k].transform_id], imgs[k].level_shift);
-      by_class[b8 ? 1 : 0].push_back(d);
       dump = dump || imgs[k].coef_out || imgs[k].scaled_out;
       pixels += static_cast<int64_t>(imgs[k].H) * imgs[k].W;
+      dimgs_all.push_back(d);
     }
+    // a plan that dumps coefficients keeps every image on a dumping kernel
+    for (int k = 0; k < n; ++k)
+      by_class[kernel_class(ctx->host[imgs[k].transform_id], imgs[k].level_shift, dump)].push_back(dimgs_all[k]);
   }
   rklt_plan* p = new (std::nothrow) rklt_plan;
   if (!p) return fail(RKLT_E_NOMEM, "rklt_plan_create: out of host memory");
@@ -476,9 +559,9 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
     delete p;
     return hip_fail("hipSetDevice", e);
   }
-  for (int c = 1; c >= 0; --c) {
+  for (int c = 2; c >= 0; --c) {
     if (by_class[c].empty()) continue;
-    st = build_part(ctx, by_class[c], c == 1, wg, bpt, grid_req, N, &p->parts[p->nparts]);
+    st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts]);
     if (st) {
       for (int k = 0; k < p->nparts; ++k) free_part(p->parts[k]);
       delete p;
@@ -505,7 +588,9 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.res = d_res;
     a.total_tiles = static_cast<int32_t>(q.total_tiles);
     a.dump = p->dump ? 1 : 0;
-    const rklt_status st = q.block8 ? launch_block8(a, q.grid, q.wg, stream) : launch_generic(p->N, a, q.grid, stream);
+    const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
+                           : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
+                                        : launch_generic(p->N, a, q.grid, stream);
     if (st) return st;
   }
   return RKLT_OK;
@@ -535,14 +620,14 @@ rklt_status rklt_plan_info(const rklt_plan* p, int64_t* tiles, int32_t* grid_wgs
   return RKLT_OK;
 }
 
-rklt_status rklt_plan_launches(const rklt_plan* p, int32_t* launches, int32_t* block8_images) {
+rklt_status rklt_plan_launches(const rklt_plan* p, int32_t* launches, int32_t* images_per_class) {
   clear_error();
   if (!p) return fail(RKLT_E_INVAL, "rklt_plan_launches: plan is NULL");
-  int32_t b8 = 0;
-  for (int k = 0; k < p->nparts; ++k)
-    if (p->parts[k].block8) b8 += p->parts[k].n;
   if (launches) *launches = p->nparts;
-  if (block8_images) *block8_images = b8;
+  if (images_per_class) {
+    images_per_class[0] = images_per_class[1] = images_per_class[2] = 0;
+    for (int k = 0; k < p->nparts; ++k) images_per_class[p->parts[k].cls] += p->parts[k].n;
+  }
   return RKLT_OK;
 }
 

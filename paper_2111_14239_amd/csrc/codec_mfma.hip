@@ -1,0 +1,274 @@
+// Matrix-core kernel of the N = 8 codec (level shift 128, transforms with a
+// small exact inverse): the same computation as the register kernel, with
+// both 2D transforms as products over the 64 pixels of a block:
+//   forward   vec(B)  = (T (x) T) vec(A - 128)            v_mfma_i32_32x32x32_i8
+//   inverse   vec(Out) = (adj (x) adj) vec(mask (.) B)      v_mfma_f32_32x32x16_f16
+// where (x) is the Kronecker product (so B = T (A - 128) T^T, exact int32) and
+// Out = adj (mask (.) B) adj^T = den^2 (A' - 128) as in the register kernel.
+//
+// A wave codes 32 blocks per step: block = lane % 32.  The forward product
+// takes 32 zig-zag ranks per instruction pair (two K-chunks of 32 pixels);
+// rows of ranks >= r are zeroed in the operand, so truncation costs nothing
+// and only ceil(r / 8) coefficient chunks enter the inverse.  Each coefficient
+// enters the fp16 inverse as two exact halves B = hi + lo (hi = B rounded to
+// fp16, |B| <= 8192 so |lo| <= 4); weights are integers |adj adj| <= 2048 and
+// every partial sum stays below 2^24 (checked on the host), so the FP32
+// accumulation is exact and Out is the exact integer.
+//
+// Operand layouts (checked on gfx950 with a lane-layout probe): A lane l holds
+// row l % 32 and K elements 16 (l / 32) + e (int8) or 8 (l / 32) + e (fp16);
+// B lane l holds column l % 32 with the same K elements; accumulator register
+// 4g + v of lane l holds row 8g + 4 (l / 32) + v, column l % 32.  With
+// h = l / 32, lane l loads pixel rows 4c + 2h and 4c + 2h + 1 of its block for
+// K-chunk c, and receives exactly those pixels back from pixel chunk mu = c,
+// so reconstruction, store and squared error stay in the lane that loaded.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.h"
+#include "rklt_internal.h"
+
+namespace rklt {
+namespace {
+
+// Occupancy target (waves per SIMD the register allocation must allow) and
+// depth of the pixel prefetch ring (steps in flight per wave, 2 or 3).
+#ifndef RKLT_MFMA_WAVES_PER_EU
+#define RKLT_MFMA_WAVES_PER_EU 3
+#endif
+#ifndef RKLT_MFMA_RING
+#define RKLT_MFMA_RING 3
+#endif
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// One step: 32 blocks of one image.  px[c][rr] are pixel rows 4c + 2h + rr
+// (8 bytes each) of this lane's block; sF the forward operand (ranks >= r
+// zeroed) and sV the inverse operand, both in LDS.  Writes the reconstruction rows
+// to d (when non-null) and accumulates the squared-error terms.
+template <int R8>
+__device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF, const v8h* sV, int lane,
+                                          float inv, float bias, uint8_t* d, int pd, bool valid, uint32_t& sxx,
+                                          uint32_t& sxy) {
+  v4i X[2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    X[c][0] = static_cast<int>(px[c][0].x ^ 0x80808080u);
+    X[c][1] = static_cast<int>(px[c][0].y ^ 0x80808080u);
+    X[c][2] = static_cast<int>(px[c][1].x ^ 0x80808080u);
+    X[c][3] = static_cast<int>(px[c][1].y ^ 0x80808080u);
+  }
+  const v16i zi = {};
+  v16i acc[2];
+  acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(0 * 2 + 0) * 64 + lane], X[0], zi, 0, 0, 0);
+  acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(0 * 2 + 1) * 64 + lane], X[1], acc[0], 0, 0, 0);
+  if (R8 > 4) {
+    acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(1 * 2 + 0) * 64 + lane], X[0], zi, 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(1 * 2 + 1) * 64 + lane], X[1], acc[1], 0, 0, 0);
+  }
+  const v16f zf = {};
+  v16f out[2] = {zf, zf};
+#pragma unroll
+  for (int kappa = 0; kappa < R8; ++kappa) {
+    const int g = kappa & 3;
+    v8h Bop;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float fb = static_cast<float>(acc[kappa >> 2][4 * g + v]);
+      const _Float16 hb = static_cast<_Float16>(fb);
+      Bop[2 * v] = hb;
+      Bop[2 * v + 1] = static_cast<_Float16>(fb - static_cast<float>(hb));
+    }
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu)
+      out[mu] = __builtin_amdgcn_mfma_f32_32x32x16_f16(sV[(mu * 8 + kappa) * 64 + lane], Bop, out[mu], 0, 0, 0);
+    // keep each chunk's operand reads next to its use (register pressure)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // Reconstruction: register 4g + v of pixel chunk mu is pixel row
+  // 4 mu + 2h + g / 2, column 4 (g % 2) + v of this lane's block.
+#pragma unroll
+  for (int mu = 0; mu < 2; ++mu) {
+    uint32_t w[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(out[mu][4 * g + v], inv, bias), v, word);
+      w[g] = word;
+    }
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      if (valid) {
+        if (d) {
+          u32x2 o;
+          o.x = w[2 * rr];
+          o.y = w[2 * rr + 1];
+          *as_global(reinterpret_cast<u32x2*>(d + static_cast<size_t>(rr) * pd + static_cast<size_t>(mu) * 4 * pd)) = o;
+        }
+        sxx = __builtin_amdgcn_udot4(px[mu][rr].x, px[mu][rr].x, sxx, false);
+        sxx = __builtin_amdgcn_udot4(px[mu][rr].y, px[mu][rr].y, sxx, false);
+        sxx = __builtin_amdgcn_udot4(w[2 * rr], w[2 * rr], sxx, false);
+        sxx = __builtin_amdgcn_udot4(w[2 * rr + 1], w[2 * rr + 1], sxx, false);
+        sxy = __builtin_amdgcn_udot4(px[mu][rr].x, w[2 * rr], sxy, false);
+        sxy = __builtin_amdgcn_udot4(px[mu][rr].y, w[2 * rr + 1], sxy, false);
+      }
+    }
+  }
+}
+
+// Pixel rows 4c + 2h + rr (c, rr in {0, 1}) of block b, or zeros.
+__device__ __forceinline__ void load_step(const DevImage* im, bool valid, int b, int bw, int ps, int h,
+                                          u32x2 (&px)[2][2]) {
+  if (valid) {
+    const int by = b / bw, bx = b - by * bw;
+    const uint8_t* s = im->src + (static_cast<size_t>(by) * 8 + 2 * h) * ps + bx * 8;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr)
+        px[c][rr] = *as_global(reinterpret_cast<const u32x2*>(s + static_cast<size_t>(4 * c + rr) * ps));
+  } else {
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) px[c][rr] = u32x2{0u, 0u};
+  }
+}
+
+// Steps [base0, be) of one image segment, 32 blocks per step, strided by
+// the workgroup's waves.  A ring of RKLT_MFMA_RING pixel buffers keeps the
+// loads of the next steps in flight while a step is computed.
+template <int R8>
+__device__ __forceinline__ void segment(const DevImage* im, int base0, int be, int stride, const v4i* sF,
+                                        const v8h* sV, int lane, int q, int h, float inv, float bias,
+                                        uint32_t& sxx, uint32_t& sxy) {
+  const int bw = im->bw, ps = im->ps, pd = im->pd;
+  uint8_t* const dst = im->dst;
+#if RKLT_MFMA_RING == 3
+  u32x2 p0[2][2], p1[2][2], p2[2][2];
+  load_step(im, base0 + q < be, base0 + q, bw, ps, h, p0);
+  load_step(im, base0 + stride + q < be, base0 + stride + q, bw, ps, h, p1);
+  load_step(im, base0 + 2 * stride + q < be, base0 + 2 * stride + q, bw, ps, h, p2);
+#else
+  u32x2 p0[2][2], p1[2][2];
+  load_step(im, base0 + q < be, base0 + q, bw, ps, h, p0);
+  load_step(im, base0 + stride + q < be, base0 + stride + q, bw, ps, h, p1);
+#endif
+  auto run = [&](u32x2 (&px)[2][2], int base) {
+    const int b = base + q;
+    const bool valid = b < be;
+    uint8_t* d = nullptr;
+    if (valid && dst) {
+      const int by = b / bw, bx = b - by * bw;
+      d = dst + (static_cast<size_t>(by) * 8 + 2 * h) * pd + bx * 8;
+    }
+    mfma_step<R8>(px, sF, sV, lane, inv, bias, d, pd, valid, sxx, sxy);
+    const int nb = b + RKLT_MFMA_RING * stride;
+    load_step(im, nb < be, nb, bw, ps, h, px);
+  };
+  for (int base = base0; base < be; base += RKLT_MFMA_RING * stride) {
+    run(p0, base);
+    if (base + stride >= be) break;
+    run(p1, base + stride);
+#if RKLT_MFMA_RING == 3
+    if (base + 2 * stride >= be) break;
+    run(p2, base + 2 * stride);
+#endif
+  }
+}
+
+// PLAN: a batch plan's work list; otherwise the plain path's single image.
+// The grid is sized to the resident capacity.  Workgroup w codes the
+// contiguous tile range [w T / G, (w + 1) T / G) as segments of consecutive
+// tiles of one image: per segment it sets up the image (forward operand with
+// ranks >= r zeroed; the inverse operand staged in LDS when the transform
+// changes), lets its waves stride over the segment's steps, and adds the
+// segment's squared error and tile count to the image's accumulator.
+template <bool PLAN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RKLT_MFMA_WAVES_PER_EU)))
+void rklt_mfma8_kernel(KArgs a) {
+  __shared__ unsigned long long red[4];
+  __shared__ v8h sV[2 * 8 * 64];  // inverse operand of the current transform (16 KB)
+  __shared__ v4i sF[2 * 2 * 64];  // forward operand of the current (transform, r) (4 KB)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = static_cast<int>(blockDim.x >> 6);
+  const int q = lane & 31, h = lane >> 5;
+  const int stride = nwaves * 32;
+  int loaded = -1, loaded_r = -1;
+  const int t_end = tile_end_of(a.total_tiles);
+  for (int t = tile_begin(a.total_tiles); t < t_end;) {
+    const int ii = PLAN ? __builtin_amdgcn_readfirstlane(a.tile_img[t]) : 0;
+    const DevImage* im = PLAN ? a.imgs + ii : &a.one;
+    const int tile0 = im->tile0, ntiles = im->ntiles;
+    const int seg_end = tile0 + ntiles < t_end ? tile0 + ntiles : t_end;
+    const int tid = __builtin_amdgcn_readfirstlane(im->tid);
+    const int r = __builtin_amdgcn_readfirstlane(im->r);
+    const DevTransform* tf = a.tf + tid;
+    if (tid != loaded || r != loaded_r) {
+      __syncthreads();
+      if (tid != loaded) {
+        const uint4* srcv = reinterpret_cast<const uint4*>(&tf->mV[0][0][0][0]);
+        uint4* dstv = reinterpret_cast<uint4*>(sV);
+        for (int k = threadIdx.x; k < 2 * 8 * 64; k += blockDim.x) dstv[k] = srcv[k];
+      }
+      // forward operand: rows (zig-zag ranks) >= r zeroed
+      for (int k = threadIdx.x; k < 2 * 2 * 64; k += blockDim.x) {
+        const int mu = k >> 7, l = k & 63;
+        const int4 f = *reinterpret_cast<const int4*>(&tf->mF[0][0][0][0] + 4 * k);
+        const bool keep = 32 * mu + (l & 31) < r;
+        sF[k] = keep ? v4i{f.x, f.y, f.z, f.w} : v4i{0, 0, 0, 0};
+      }
+      __syncthreads();
+      loaded = tid;
+      loaded_r = r;
+    }
+    const int R8 = (r + 7) >> 3;
+    const float inv = tf->inv_den2, bias = tf->bias;
+    const int tb = im->tile_blocks, nblocks = im->nblocks;
+    const int bs = (t - tile0) * tb;
+    const int be = (seg_end - tile0) * tb < nblocks ? (seg_end - tile0) * tb : nblocks;
+    uint32_t sxx = 0, sxy = 0;
+    const int base0 = bs + wave * 32;
+    switch (R8) {
+      case 1: segment<1>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      case 2: segment<2>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      case 3: segment<3>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      case 4: segment<4>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      case 5: segment<5>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      case 6: segment<6>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      case 7: segment<7>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      default: segment<8>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+    }
+    reduce_and_finish(sxx - 2u * sxy, red, a.res + im->slot, seg_end - t, ntiles,
+                      static_cast<long long>(im->H) * im->W);
+    t = seg_end;
+  }
+}
+
+rklt_status launched_mfma() {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RKLT_E_HIP, "rklt_mfma8_kernel: launch failed: %s", hipGetErrorString(e));
+  return RKLT_OK;
+}
+
+}  // namespace
+
+int mfma8_resident_wgs_per_cu(int wg) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rklt_mfma8_kernel<true>, wg, 0) != hipSuccess) return 0;
+  return n;
+}
+
+rklt_status launch_mfma8(const KArgs& a, int grid, int wg, void* stream) {
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (a.imgs) hipLaunchKernelGGL(rklt_mfma8_kernel<true>, dim3(grid), dim3(wg), 0, st, a);
+  else hipLaunchKernelGGL(rklt_mfma8_kernel<false>, dim3(grid), dim3(wg), 0, st, a);
+  return launched_mfma();
+}
+
+}  // namespace rklt

@@ -40,6 +40,18 @@ struct alignas(256) DevTransform {
   float inv_den2, bias;
   int32_t adj[64];
   float fadj[64];                // m*8 + i
+  // N = 8 matrix-core operands, in the lane layout of the instructions
+  // (mfma = 1 when the exact inverse also fits fp16 operands; see abi.cpp):
+  //   mF[mu][c][lane][w]   forward A operand of v_mfma_i32_32x32x32_i8, int8x4
+  //                        words: row = zig-zag rank 32 mu + lane % 32, K =
+  //                        pixel of K-chunk c; value T[i][m] T[j][n]
+  //   mV[mu][kappa][lane]  inverse A operand of v_mfma_f32_32x32x16_f16, 8 halves:
+  //                        row = pixel of chunk mu, K = (rank, hi/lo part) of
+  //                        coefficient chunk kappa; value adj[m][i] adj[n][j]
+  int32_t mfma;
+  int32_t pad_mfma[3];
+  int32_t mF[2][2][64][4];
+  _Float16 mV[2][8][64][8];
   float w[RKLT_MAX_N * RKLT_MAX_N];     // s_i s_j at i*N + j
   float G[RKLT_MAX_N * RKLT_MAX_N];     // T_hat^-1 at m*N + i
   float Ti[RKLT_MAX_N * RKLT_MAX_N];    // T^-1 = T_hat^-1 S at m*N + i
@@ -85,6 +97,8 @@ inline int diagonals_for(int N, int r) {
 
 // Kernel launchers (codec.hip).
 rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream);
+rklt_status launch_mfma8(const KArgs& a, int grid, int wg, void* stream);
+int mfma8_resident_wgs_per_cu(int wg);
 rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream);
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
 int generic_blocks_per_tile(int N);

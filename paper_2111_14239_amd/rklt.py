@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librklt.so")
+# RKLT_LIBRARY may name another build of the same library (tuning experiments);
+# by default the in-tree build is loaded.
+LIB_PATH = os.environ.get("RKLT_LIBRARY") or os.path.join(_HERE, "librklt.so")
 
 MAX_N = 32
 ORTHOGONAL = 1
@@ -88,7 +90,7 @@ def _load():
         "rklt_plan_destroy": (st, [vp]),
         "rklt_plan_info": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_copy_bytes": (st, [vp, vp, C.c_size_t, vp]),
-        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 3)]),
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -279,9 +281,11 @@ class Plan:
         tiles, grid, pixels = C.c_int64(), C.c_int32(), C.c_int64()
         _check(_lib.rklt_plan_info(h, C.byref(tiles), C.byref(grid), C.byref(pixels)))
         self.tiles, self.grid, self.pixels = int(tiles.value), int(grid.value), int(pixels.value)
-        nl, nb8 = C.c_int32(), C.c_int32()
-        _check(_lib.rklt_plan_launches(h, C.byref(nl), C.byref(nb8)))
-        self.launches, self.block8_images = int(nl.value), int(nb8.value)
+        nl, per = C.c_int32(), (C.c_int32 * 3)()
+        _check(_lib.rklt_plan_launches(h, C.byref(nl), per))
+        self.launches = int(nl.value)
+        self.images_per_class = [int(v) for v in per]  # [generic, register N=8, matrix-core N=8]
+        self.block8_images = self.images_per_class[1] + self.images_per_class[2]
 
     def run(self, res_ptr: int, stream=None):
         _check(_lib.rklt_plan_run(self._h, C.c_void_p(res_ptr), C.c_void_p(_stream_handle(stream))))

@@ -331,11 +331,32 @@ def test_exact_inverse_coverage(ctx):
         check_against_oracle(img, 8, 0.1, 3.0, r, 128, got)
 
 
-def test_plan_takes_register_kernel_for_every_n8_image(ctx):
+def test_plan_kernel_classes(ctx):
+    # every N = 8 image with level shift 128 takes an N = 8 kernel: the
+    # matrix-core one when its transform has a small exact inverse, the
+    # register one otherwise (alpha = 3, rho = 0.1)
     specs = [(64, 64, rho, a, 10, 30 + k, 128) for k, (rho, a) in enumerate(N8_CASES + [(0.1, 3.0)])]
     xs, dsts, plan, res = _batch(ctx, specs)
-    assert plan.launches == 1 and plan.block8_images == len(specs)
+    assert plan.launches == 2 and plan.images_per_class == [0, 1, len(N8_CASES)]
+    plan.run(int(res.data_ptr()))
+    torch.cuda.synchronize()
+    for (img, x), d, g, spec in zip(xs, dsts, rklt.read_results(res), specs):
+        H, W, rho, alpha, r, seed, ell = spec
+        g.update(recon=d.cpu().numpy(), coef=None, exact=is_exact(ctx, 8, rho, alpha, ell))
+        check_against_oracle(img, 8, rho, alpha, r, ell, g, check_coef=False)
     plan.close()
+
+
+@pytest.mark.parametrize("rho,alpha", N8_CASES)
+def test_matrix_core_and_register_kernels_agree(ctx, rho, alpha):
+    # the plain path codes without a dump on the matrix-core kernel and with
+    # a dump on the register kernel; both reconstruct exactly
+    img = ar1_image(136, 264, rho, seed=41)
+    for r in (1, 8, 9, 32, 33, 57, 64):
+        a = run_plain(ctx, img, 8, rho, alpha, r, dump=False)
+        b = run_plain(ctx, img, 8, rho, alpha, r, dump=True)
+        assert np.array_equal(a["recon"], b["recon"]) and a["sse"] == b["sse"], r
+        check_against_oracle(img, 8, rho, alpha, r, 128, a, check_coef=False)
 
 
 def test_copy_probe(ctx):
