@@ -45,7 +45,7 @@ def _gen(spec):
 
 def _source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("codec.hip", "rklt_internal.h"):
+    for f in ("codec_mfma.hip", "device_common.h", "rklt_internal.h"):
         with open(os.path.join(ROOT, "paper_2111_14239_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -54,7 +54,7 @@ def _source_hash() -> str:
 def _traffic(pixels: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "block8_batch256_1024_traffic.json")
+    path = os.path.join(ROOT, "profiles", "mfma8_batch_1024_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:

@@ -2,6 +2,7 @@
 // validation, plans (device work lists) and launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -24,6 +25,7 @@ struct rklt_ctx {
 // One launch of a plan: the images of one kernel class.
 struct PlanPart {
   int cls = 0;  // kernel class (see kernel_class)
+  int32_t* d_wg_tiles = nullptr;  // matrix-core class: per-workgroup tile ranges
   int n = 0;
   rklt::DevImage* d_imgs = nullptr;
   int32_t* d_tile_img = nullptr;
@@ -125,6 +127,29 @@ rklt_status check_image(rklt_ctx* ctx, const rklt_image& im, int index, DevImage
   d.nblocks = (im.H / N) * (im.W / N);
   *N_out = N;
   return RKLT_OK;
+}
+
+// Forward operand of the matrix-core kernel (v_mfma_i32_32x32x32_i8 A
+// operand): lane `lane` of row chunk mu and K-chunk c holds 16 int8 weights
+// T[i][m] T[j][n] of the coefficient (i, j) with zig-zag rank 32 mu + lane % 32
+// against the pixels (m, n) of rows 4c + 2 (lane / 32) + e / 8, column e % 8.
+void fill_forward_operand(const int32_t* T, const int32_t* order, int32_t (&mF)[2][2][64][4]) {
+  for (int mu = 0; mu < 2; ++mu)
+    for (int c = 0; c < 2; ++c)
+      for (int lane = 0; lane < 64; ++lane) {
+        const int o = order[32 * mu + (lane & 31)];
+        const int i = o / 8, j = o % 8;
+        for (int w = 0; w < 4; ++w) {
+          uint32_t word = 0;
+          for (int b = 0; b < 4; ++b) {
+            const int e = 4 * w + b;
+            const int row = 4 * c + 2 * (lane >> 5) + e / 8, col = e % 8;
+            const int v = T[i * 8 + row] * T[j * 8 + col];
+            word |= (static_cast<uint32_t>(v) & 0xffu) << (8 * b);
+          }
+          mF[mu][c][lane][w] = static_cast<int32_t>(word);
+        }
+      }
 }
 
 // Blocks per tile for one image: the launch's tile size, grown (in steps of
@@ -320,20 +345,30 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
       }
     }
   }
-  if (N == 8 && dt.exact) {
-    // Matrix-core operands.  Exactness needs: forward weights T_im T_jn in
-    // int8; |B| <= 32768 so that B = hi + lo with hi = fp16(B) and |lo| <= 8,
-    // both exact in fp16; inverse weights adj_mi adj_nj exact fp16 integers
-    // (|.| <= 2048); and every partial sum of the inverse below 2^24, bounded
-    // by sum_ij |adj_mi adj_nj| (Bmax_ij + 16).
+  if (N == 8 && !dt.exact) {
+    dt.den = 0;
+    dt.inv_den2 = 1.0f;
+    dt.bias = 128.0f + 1.0f / 4096.0f;
+    for (int k = 0; k < 64; ++k) dt.fadj[k] = dt.Ti[k];
+  }
+  if (N == 8 && max_abs * max_abs <= 127) {
+    // Matrix-core operands.  The forward weights T_im T_jn fit int8.  The
+    // inverse takes one of two forms (DevTransform::mfma):
+    //   1  exact, fp16: needs an exact inverse with |B| <= 32768 (so that
+    //      B = hi + lo, hi = fp16(B), |lo| <= 8, both exact in fp16), weights
+    //      adj_mi adj_nj exact fp16 integers (|.| <= 2048) and every partial
+    //      sum below 2^24, bounded by sum_ij |adj_mi adj_nj| (Bmax_ij + 16);
+    //   2  FP32 (v_mfma_f32_32x32x2_f32) with the weights that match the
+    //      epilogue constants: adj (x) adj when exact, else T^-1 (x) T^-1.
     int32_t order[64];
     zigzag(8, order);
+    fill_forward_operand(t->T, order, dt.mF);
     double L1[8];
     for (int i = 0; i < 8; ++i) {
       L1[i] = 0;
       for (int j = 0; j < 8; ++j) L1[i] += std::abs(t->T[i * 8 + j]);
     }
-    bool ok = max_abs * max_abs <= 127;
+    bool ok = dt.exact != 0;
     double omax = 0;
     for (int m = 0; m < 8 && ok; ++m)
       for (int n = 0; n < 8 && ok; ++n) {
@@ -347,43 +382,30 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
           }
         omax = std::fmax(omax, o);
       }
-    if (ok && omax < 16777216.0) {
-      dt.mfma = 1;
-      for (int mu = 0; mu < 2; ++mu)
-        for (int c = 0; c < 2; ++c)
-          for (int lane = 0; lane < 64; ++lane) {
-            const int o = order[32 * mu + (lane & 31)];
-            const int i = o / 8, j = o % 8;
-            for (int w = 0; w < 4; ++w) {
-              uint32_t word = 0;
-              for (int b = 0; b < 4; ++b) {
-                const int e = 4 * w + b;
-                const int row = 4 * c + 2 * (lane >> 5) + e / 8, col = e % 8;
-                const int v = t->T[i * 8 + row] * t->T[j * 8 + col];
-                word |= (static_cast<uint32_t>(v) & 0xffu) << (8 * b);
-              }
-              dt.mF[mu][c][lane][w] = static_cast<int32_t>(word);
-            }
-          }
-      for (int mu = 0; mu < 2; ++mu)
-        for (int kappa = 0; kappa < 8; ++kappa)
-          for (int lane = 0; lane < 64; ++lane) {
-            const int M = lane & 31;
-            const int g = M >> 3, hm = (M >> 2) & 1, v = M & 3;
-            const int m = 4 * mu + 2 * hm + g / 2, n = 4 * (g % 2) + v;
+    dt.mfma = (ok && omax < 16777216.0) ? 1 : 2;
+    for (int mu = 0; mu < 2; ++mu)
+      for (int kappa = 0; kappa < 8; ++kappa)
+        for (int lane = 0; lane < 64; ++lane) {
+          // A-operand row: pixel M = lane % 32 of pixel chunk mu
+          const int M = lane & 31;
+          const int g = M >> 3, hm = (M >> 2) & 1, vm = M & 3;
+          const int m = 4 * mu + 2 * hm + g / 2, n = 4 * (g % 2) + vm;
+          if (dt.mfma == 1) {
             for (int e = 0; e < 8; ++e) {
               const int o = order[8 * kappa + 4 * (lane >> 5) + e / 2];
               const int i = o / 8, j = o % 8;
               dt.mV[mu][kappa][lane][e] = static_cast<_Float16>(static_cast<float>(dt.adj[m * 8 + i] * dt.adj[n * 8 + j]));
             }
+          } else {
+            for (int v = 0; v < 4; ++v) {
+              const int o = order[8 * kappa + 4 * (lane >> 5) + v];
+              const int i = o / 8, j = o % 8;
+              const double w = dt.exact ? static_cast<double>(dt.adj[m * 8 + i]) * dt.adj[n * 8 + j]
+                                        : static_cast<double>(t->G[m * 8 + i]) * t->s[i] * t->G[n * 8 + j] * t->s[j];
+              dt.mVf[mu][kappa][v][lane] = static_cast<float>(w);
+            }
           }
-    }
-  }
-  if (N == 8 && !dt.exact) {
-    dt.den = 0;
-    dt.inv_den2 = 1.0f;
-    dt.bias = 128.0f + 1.0f / 4096.0f;
-    for (int k = 0; k < 64; ++k) dt.fadj[k] = dt.Ti[k];
+        }
   }
   if (N == 8 && max_abs <= 127) {
     for (int j = 0; j < 8; ++j) {
@@ -464,8 +486,19 @@ namespace {
 void free_part(PlanPart& q) {
   (void)hipFree(q.d_imgs);
   (void)hipFree(q.d_tile_img);
+  (void)hipFree(q.d_wg_tiles);
   q.d_imgs = nullptr;
   q.d_tile_img = nullptr;
+  q.d_wg_tiles = nullptr;
+}
+
+// Relative cost of one N x N block in the matrix-core kernel, measured on
+// MI355X for each inverse form and number R8 = ceil(r / 8) of 8-coefficient
+// chunks: a fixed part per step plus a part per chunk (the FP32 form runs
+// eight 32x32x2 products per chunk).
+double mfma8_block_cost(int path, int r) {
+  const int R8 = (r + 7) / 8;
+  return path == 1 ? 0.0760 + 0.0030 * R8 : 0.0626 + 0.0182 * R8;
 }
 
 // Tile the images of one kernel class and upload the work list.
@@ -505,8 +538,40 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
     free_part(*q);
     return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
   }
+  std::vector<int32_t> wg_tiles;
+  if (cls == 2 && q->grid > 0) {
+    // Split the tiles into grid contiguous ranges of (nearly) equal estimated
+    // cost: range w ends at the first tile where the running cost reaches
+    // (w + 1) / grid of the total.
+    std::vector<double> cost(static_cast<size_t>(total));
+    double sum = 0;
+    for (size_t k = 0; k < imgs.size(); ++k) {
+      const double c = mfma8_block_cost(ctx->host[imgs[k].tid].mfma, imgs[k].r);
+      for (int t = 0; t < imgs[k].ntiles; ++t) {
+        const int64_t b0 = static_cast<int64_t>(t) * imgs[k].tile_blocks;
+        const int64_t nb = std::min<int64_t>(imgs[k].tile_blocks, imgs[k].nblocks - b0);
+        cost[imgs[k].tile0 + t] = c * static_cast<double>(nb);
+        sum += c * static_cast<double>(nb);
+      }
+    }
+    wg_tiles.assign(static_cast<size_t>(q->grid) + 1, static_cast<int32_t>(total));
+    wg_tiles[0] = 0;
+    double run = 0;
+    int w = 1;
+    for (int64_t t = 0; t < total && w < q->grid; ++t) {
+      run += cost[t];
+      while (w < q->grid && run >= sum * w / q->grid) wg_tiles[w++] = static_cast<int32_t>(t + 1);
+    }
+    e = hipMalloc(&q->d_wg_tiles, sizeof(int32_t) * wg_tiles.size());
+    if (e != hipSuccess) {
+      free_part(*q);
+      return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
+    }
+  }
   e = hipMemcpy(q->d_imgs, imgs.data(), sizeof(DevImage) * imgs.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(q->d_tile_img, tile_img.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
+  if (e == hipSuccess && q->d_wg_tiles)
+    e = hipMemcpy(q->d_wg_tiles, wg_tiles.data(), sizeof(int32_t) * wg_tiles.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     free_part(*q);
     return hip_fail("rklt_plan_create: hipMemcpy", e);
@@ -584,6 +649,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     std::memset(&a, 0, sizeof(a));
     a.imgs = q.d_imgs;
     a.tile_img = q.d_tile_img;
+    a.wg_tiles = q.d_wg_tiles;
     a.tf = p->ctx->d_table;
     a.res = d_res;
     a.total_tiles = static_cast<int32_t>(q.total_tiles);

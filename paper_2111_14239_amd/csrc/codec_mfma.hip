@@ -1,8 +1,11 @@
-// Matrix-core kernel of the N = 8 codec (level shift 128, transforms with a
-// small exact inverse): the same computation as the register kernel, with
-// both 2D transforms as products over the 64 pixels of a block:
+// Matrix-core kernel of the N = 8 codec (level shift 128, int8-range T): the
+// same computation as the register kernel, with both 2D transforms as
+// products over the 64 pixels of a block:
 //   forward   vec(B)  = (T (x) T) vec(A - 128)            v_mfma_i32_32x32x32_i8
 //   inverse   vec(Out) = (adj (x) adj) vec(mask (.) B)      v_mfma_f32_32x32x16_f16
+// (transforms without a small exact inverse take the FP32 form
+//   vec(A' - 128) = (T^-1 (x) T^-1) vec(mask (.) B)        v_mfma_f32_32x32x2_f32
+// with FP32 accuracy, like the register kernel's fallback)
 // where (x) is the Kronecker product (so B = T (A - 128) T^T, exact int32) and
 // Out = adj (mask (.) B) adj^T = den^2 (A' - 128) as in the register kernel.
 //
@@ -50,8 +53,8 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // (8 bytes each) of this lane's block; sF the forward operand (ranks >= r
 // zeroed) and sV the inverse operand, both in LDS.  Writes the reconstruction rows
 // to d (when non-null) and accumulates the squared-error terms.
-template <int R8>
-__device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF, const v8h* sV, int lane,
+template <int R8, int PATH>
+__device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF, const void* sVraw, int lane,
                                           float inv, float bias, uint8_t* d, int pd, bool valid, uint32_t& sxx,
                                           uint32_t& sxy) {
   v4i X[2];
@@ -72,22 +75,42 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
   }
   const v16f zf = {};
   v16f out[2] = {zf, zf};
+  if (PATH == 1) {
+    // exact fp16 inverse: each coefficient as two exact halves B = hi + lo
+    const v8h* sV = static_cast<const v8h*>(sVraw);
 #pragma unroll
-  for (int kappa = 0; kappa < R8; ++kappa) {
-    const int g = kappa & 3;
-    v8h Bop;
+    for (int kappa = 0; kappa < R8; ++kappa) {
+      const int g = kappa & 3;
+      v8h Bop;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const float fb = static_cast<float>(acc[kappa >> 2][4 * g + v]);
-      const _Float16 hb = static_cast<_Float16>(fb);
-      Bop[2 * v] = hb;
-      Bop[2 * v + 1] = static_cast<_Float16>(fb - static_cast<float>(hb));
+      for (int v = 0; v < 4; ++v) {
+        const float fb = static_cast<float>(acc[kappa >> 2][4 * g + v]);
+        const _Float16 hb = static_cast<_Float16>(fb);
+        Bop[2 * v] = hb;
+        Bop[2 * v + 1] = static_cast<_Float16>(fb - static_cast<float>(hb));
+      }
+#pragma unroll
+      for (int mu = 0; mu < 2; ++mu)
+        out[mu] = __builtin_amdgcn_mfma_f32_32x32x16_f16(sV[(mu * 8 + kappa) * 64 + lane], Bop, out[mu], 0, 0, 0);
+      // keep each chunk's operand reads next to its use (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
     }
+  } else {
+    // FP32 inverse: one coefficient per lane and instruction (K = lane / 32)
+    const float* sVf = static_cast<const float*>(sVraw);
 #pragma unroll
-    for (int mu = 0; mu < 2; ++mu)
-      out[mu] = __builtin_amdgcn_mfma_f32_32x32x16_f16(sV[(mu * 8 + kappa) * 64 + lane], Bop, out[mu], 0, 0, 0);
-    // keep each chunk's operand reads next to its use (register pressure)
-    __builtin_amdgcn_sched_barrier(0);
+    for (int kappa = 0; kappa < R8; ++kappa) {
+      const int g = kappa & 3;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float fb = static_cast<float>(acc[kappa >> 2][4 * g + v]);
+#pragma unroll
+        for (int mu = 0; mu < 2; ++mu)
+          out[mu] = __builtin_amdgcn_mfma_f32_32x32x2f32(sVf[((mu * 8 + kappa) * 4 + v) * 64 + lane], fb, out[mu], 0, 0,
+                                                         0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   // Reconstruction: register 4g + v of pixel chunk mu is pixel row
   // 4 mu + 2h + g / 2, column 4 (g % 2) + v of this lane's block.
@@ -143,9 +166,9 @@ __device__ __forceinline__ void load_step(const DevImage* im, bool valid, int b,
 // Steps [base0, be) of one image segment, 32 blocks per step, strided by
 // the workgroup's waves.  A ring of RKLT_MFMA_RING pixel buffers keeps the
 // loads of the next steps in flight while a step is computed.
-template <int R8>
+template <int R8, int PATH>
 __device__ __forceinline__ void segment(const DevImage* im, int base0, int be, int stride, const v4i* sF,
-                                        const v8h* sV, int lane, int q, int h, float inv, float bias,
+                                        const void* sV, int lane, int q, int h, float inv, float bias,
                                         uint32_t& sxx, uint32_t& sxy) {
   const int bw = im->bw, ps = im->ps, pd = im->pd;
   uint8_t* const dst = im->dst;
@@ -167,7 +190,7 @@ __device__ __forceinline__ void segment(const DevImage* im, int base0, int be, i
       const int by = b / bw, bx = b - by * bw;
       d = dst + (static_cast<size_t>(by) * 8 + 2 * h) * pd + bx * 8;
     }
-    mfma_step<R8>(px, sF, sV, lane, inv, bias, d, pd, valid, sxx, sxy);
+    mfma_step<R8, PATH>(px, sF, sV, lane, inv, bias, d, pd, valid, sxx, sxy);
     const int nb = b + RKLT_MFMA_RING * stride;
     load_step(im, nb < be, nb, bw, ps, h, px);
   };
@@ -183,9 +206,10 @@ __device__ __forceinline__ void segment(const DevImage* im, int base0, int be, i
 }
 
 // PLAN: a batch plan's work list; otherwise the plain path's single image.
-// The grid is sized to the resident capacity.  Workgroup w codes the
-// contiguous tile range [w T / G, (w + 1) T / G) as segments of consecutive
-// tiles of one image: per segment it sets up the image (forward operand with
+// The grid is sized to the resident capacity.  Workgroup w codes a
+// contiguous tile range (the plan balances the ranges by estimated cost;
+// otherwise [w T / G, (w + 1) T / G)) as segments of consecutive tiles of one
+// image: per segment it sets up the image (forward operand with
 // ranks >= r zeroed; the inverse operand staged in LDS when the transform
 // changes), lets its waves stride over the segment's steps, and adds the
 // segment's squared error and tile count to the image's accumulator.
@@ -193,15 +217,17 @@ template <bool PLAN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RKLT_MFMA_WAVES_PER_EU)))
 void rklt_mfma8_kernel(KArgs a) {
   __shared__ unsigned long long red[4];
-  __shared__ v8h sV[2 * 8 * 64];  // inverse operand of the current transform (16 KB)
+  __shared__ uint4 sV[2 * 8 * 64];  // inverse operand of the current transform (16 KB)
   __shared__ v4i sF[2 * 2 * 64];  // forward operand of the current (transform, r) (4 KB)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = static_cast<int>(blockDim.x >> 6);
   const int q = lane & 31, h = lane >> 5;
   const int stride = nwaves * 32;
   int loaded = -1, loaded_r = -1;
-  const int t_end = tile_end_of(a.total_tiles);
-  for (int t = tile_begin(a.total_tiles); t < t_end;) {
+  // contiguous tile range of this workgroup: cost-balanced by the plan, or an
+  // equal share of the tiles
+  const int t_end = PLAN && a.wg_tiles ? a.wg_tiles[blockIdx.x + 1] : tile_end_of(a.total_tiles);
+  for (int t = PLAN && a.wg_tiles ? a.wg_tiles[blockIdx.x] : tile_begin(a.total_tiles); t < t_end;) {
     const int ii = PLAN ? __builtin_amdgcn_readfirstlane(a.tile_img[t]) : 0;
     const DevImage* im = PLAN ? a.imgs + ii : &a.one;
     const int tile0 = im->tile0, ntiles = im->ntiles;
@@ -212,9 +238,10 @@ void rklt_mfma8_kernel(KArgs a) {
     if (tid != loaded || r != loaded_r) {
       __syncthreads();
       if (tid != loaded) {
-        const uint4* srcv = reinterpret_cast<const uint4*>(&tf->mV[0][0][0][0]);
-        uint4* dstv = reinterpret_cast<uint4*>(sV);
-        for (int k = threadIdx.x; k < 2 * 8 * 64; k += blockDim.x) dstv[k] = srcv[k];
+        // the inverse operand of the transform's path (fp16 split or FP32), 16 KB either way
+        const uint4* srcv = tf->mfma == 1 ? reinterpret_cast<const uint4*>(&tf->mV[0][0][0][0])
+                                          : reinterpret_cast<const uint4*>(&tf->mVf[0][0][0][0]);
+        for (int k = threadIdx.x; k < 2 * 8 * 64; k += blockDim.x) sV[k] = srcv[k];
       }
       // forward operand: rows (zig-zag ranks) >= r zeroed
       for (int k = threadIdx.x; k < 2 * 2 * 64; k += blockDim.x) {
@@ -234,16 +261,20 @@ void rklt_mfma8_kernel(KArgs a) {
     const int be = (seg_end - tile0) * tb < nblocks ? (seg_end - tile0) * tb : nblocks;
     uint32_t sxx = 0, sxy = 0;
     const int base0 = bs + wave * 32;
+    const int path = __builtin_amdgcn_readfirstlane(tf->mfma);
+#define RKLT_SEG(RR)                                                                        \
+  case RR:                                                                                  \
+    if (path == 1) segment<RR, 1>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); \
+    else segment<RR, 2>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);           \
+    break;
     switch (R8) {
-      case 1: segment<1>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      case 2: segment<2>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      case 3: segment<3>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      case 4: segment<4>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      case 5: segment<5>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      case 6: segment<6>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      case 7: segment<7>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
-      default: segment<8>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); break;
+      RKLT_SEG(1) RKLT_SEG(2) RKLT_SEG(3) RKLT_SEG(4) RKLT_SEG(5) RKLT_SEG(6) RKLT_SEG(7)
+      default:
+        if (path == 1) segment<8, 1>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
+        else segment<8, 2>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
+        break;
     }
+#undef RKLT_SEG
     reduce_and_finish(sxx - 2u * sxy, red, a.res + im->slot, seg_end - t, ntiles,
                       static_cast<long long>(im->H) * im->W);
     t = seg_end;

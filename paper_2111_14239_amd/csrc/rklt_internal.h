@@ -48,10 +48,15 @@ struct alignas(256) DevTransform {
   //   mV[mu][kappa][lane]  inverse A operand of v_mfma_f32_32x32x16_f16, 8 halves:
   //                        row = pixel of chunk mu, K = (rank, hi/lo part) of
   //                        coefficient chunk kappa; value adj[m][i] adj[n][j]
+  //   mVf[mu][kappa][v][lane] inverse A operand of v_mfma_f32_32x32x2_f32 for
+  //                        transforms without a small exact inverse (exact =
+  //                        0): row = pixel, K = lane / 32 selects rank
+  //                        8 kappa + 4 (lane / 32) + v; value (T^-1 (x) T^-1) in FP32
   int32_t mfma;
   int32_t pad_mfma[3];
   int32_t mF[2][2][64][4];
   _Float16 mV[2][8][64][8];
+  float mVf[2][8][4][64];
   float w[RKLT_MAX_N * RKLT_MAX_N];     // s_i s_j at i*N + j
   float G[RKLT_MAX_N * RKLT_MAX_N];     // T_hat^-1 at m*N + i
   float Ti[RKLT_MAX_N * RKLT_MAX_N];    // T^-1 = T_hat^-1 S at m*N + i
@@ -77,6 +82,7 @@ struct DevImage {
 struct KArgs {
   const DevImage* imgs;      // plan images, or nullptr for the plain path
   const int32_t* tile_img;   // image index of every tile (plan only)
+  const int32_t* wg_tiles;   // matrix-core plans: tile range [wg_tiles[w], wg_tiles[w+1]) of workgroup w
   const DevTransform* tf;    // context transform table
   rklt_result* res;          // one per image
   int32_t total_tiles;
