@@ -181,6 +181,16 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n,
                              const rklt_tuning* tuning, rklt_plan** out);
 /* d_res: n device rklt_result, in the order of the plan's images. */
 rklt_status rklt_plan_run(rklt_plan* plan, rklt_result* d_res, void* stream);
+/* Replace the plan's images with `n` new ones (same rules as
+ * rklt_plan_create; the tuning given at creation is kept) without a
+ * synchronous copy: the work list is rebuilt on the host and uploaded with an
+ * asynchronous copy on `stream`, from pinned host memory the plan owns, into
+ * the plan's device buffer (grown only when it is too small).  The plan must
+ * not be in flight: its previous run (and update) must have completed, e.g.
+ * observed through an event recorded after the run.  A run on `stream` after
+ * the update sees the new images.  On error the plan holds no images and
+ * rklt_plan_run fails with E_STATE until a successful update. */
+rklt_status rklt_plan_update(rklt_plan* plan, const rklt_image* imgs, int32_t n, void* stream);
 rklt_status rklt_plan_destroy(rklt_plan* plan);
 /* Number of tiles and of workgroups the plan launches (for reporting). */
 rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_wgs,

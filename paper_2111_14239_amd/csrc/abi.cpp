@@ -22,16 +22,17 @@ struct rklt_ctx {
   std::mutex mu;
 };
 
-// One launch of a plan: the images of one kernel class.
+// One launch of a plan: the images of one kernel class.  The offsets locate
+// its work list (DevImage[n], tile -> image table, per-workgroup tile ranges)
+// in the plan's device buffer.
 struct PlanPart {
   int cls = 0;  // kernel class (see kernel_class)
-  int32_t* d_wg_tiles = nullptr;  // matrix-core class: per-workgroup tile ranges
   int n = 0;
-  rklt::DevImage* d_imgs = nullptr;
-  int32_t* d_tile_img = nullptr;
   int64_t total_tiles = 0;
   int wg = 256;
   int grid = 0;
+  size_t off_imgs = 0, off_tile_img = 0, off_wg_tiles = 0;
+  bool has_wg_tiles = false;
 };
 
 struct rklt_plan {
@@ -42,6 +43,15 @@ struct rklt_plan {
   int nparts = 0;
   PlanPart parts[3];
   int64_t pixels = 0;
+  rklt_tuning tuning{};
+  bool has_tuning = false;
+  // device work list and its host image (pinned when the plan is updated
+  // asynchronously)
+  void* d_buf = nullptr;
+  size_t d_cap = 0;
+  std::vector<unsigned char> h_image;
+  void* h_pinned = nullptr;
+  size_t h_cap = 0;
 };
 
 namespace rklt {
@@ -483,15 +493,6 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
 
 namespace {
 
-void free_part(PlanPart& q) {
-  (void)hipFree(q.d_imgs);
-  (void)hipFree(q.d_tile_img);
-  (void)hipFree(q.d_wg_tiles);
-  q.d_imgs = nullptr;
-  q.d_tile_img = nullptr;
-  q.d_wg_tiles = nullptr;
-}
-
 // Relative cost of one N x N block in the matrix-core kernel, measured on
 // MI355X for each inverse form and number R8 = ceil(r / 8) of 8-coefficient
 // chunks: a fixed part per step plus a part per chunk (the FP32 form runs
@@ -501,9 +502,12 @@ double mfma8_block_cost(int path, int r) {
   return path == 1 ? 0.0760 + 0.0030 * R8 : 0.0626 + 0.0182 * R8;
 }
 
-// Tile the images of one kernel class and upload the work list.
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+// Tile the images of one kernel class and append its work list to `img`
+// (the plan's host image of the device buffer).
 rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int N,
-                       PlanPart* q) {
+                       PlanPart* q, std::vector<unsigned char>& img) {
   const bool b8 = cls > 0;
   const int base = cls == 2 ? (wg / 2) * bpt : b8 ? wg * bpt : generic_blocks_per_tile(N);
   const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : generic_blocks_per_iteration(N);
@@ -514,10 +518,7 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
     d.ntiles = (d.nblocks + d.tile_blocks - 1) / d.tile_blocks;
     total += d.ntiles;
   }
-  if (total >= (int64_t{1} << 31)) return fail(RKLT_E_INVAL, "rklt_plan_create: too many tiles");
-  std::vector<int32_t> tile_img(static_cast<size_t>(total));
-  for (size_t k = 0; k < imgs.size(); ++k)
-    for (int t = 0; t < imgs[k].ntiles; ++t) tile_img[imgs[k].tile0 + t] = static_cast<int32_t>(k);
+  if (total >= (int64_t{1} << 31)) return fail(RKLT_E_INVAL, "rklt_plan: too many tiles");
   q->cls = cls;
   q->n = static_cast<int>(imgs.size());
   q->total_tiles = total;
@@ -532,14 +533,13 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
   }
   q->grid = grid_req > 0 ? grid_req : auto_grid;
   if (q->grid > total) q->grid = static_cast<int>(total);
-  hipError_t e = hipMalloc(&q->d_imgs, sizeof(DevImage) * imgs.size());
-  if (e == hipSuccess) e = hipMalloc(&q->d_tile_img, sizeof(int32_t) * total);
-  if (e != hipSuccess) {
-    free_part(*q);
-    return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
-  }
+
+  std::vector<int32_t> tile_img(static_cast<size_t>(total));
+  for (size_t k = 0; k < imgs.size(); ++k)
+    for (int t = 0; t < imgs[k].ntiles; ++t) tile_img[imgs[k].tile0 + t] = static_cast<int32_t>(k);
   std::vector<int32_t> wg_tiles;
-  if (cls == 2 && q->grid > 0) {
+  q->has_wg_tiles = cls == 2 && q->grid > 0;
+  if (q->has_wg_tiles) {
     // Split the tiles into grid contiguous ranges of (nearly) equal estimated
     // cost: range w ends at the first tile where the running cost reaches
     // (w + 1) / grid of the total.
@@ -562,35 +562,28 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
       run += cost[t];
       while (w < q->grid && run >= sum * w / q->grid) wg_tiles[w++] = static_cast<int32_t>(t + 1);
     }
-    e = hipMalloc(&q->d_wg_tiles, sizeof(int32_t) * wg_tiles.size());
-    if (e != hipSuccess) {
-      free_part(*q);
-      return fail(RKLT_E_NOMEM, "rklt_plan_create: hipMalloc: %s", hipGetErrorString(e));
-    }
   }
-  e = hipMemcpy(q->d_imgs, imgs.data(), sizeof(DevImage) * imgs.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(q->d_tile_img, tile_img.data(), sizeof(int32_t) * total, hipMemcpyHostToDevice);
-  if (e == hipSuccess && q->d_wg_tiles)
-    e = hipMemcpy(q->d_wg_tiles, wg_tiles.data(), sizeof(int32_t) * wg_tiles.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    free_part(*q);
-    return hip_fail("rklt_plan_create: hipMemcpy", e);
-  }
+  auto append = [&img](const void* src, size_t bytes) {
+    const size_t off = align256(img.size());
+    img.resize(off + bytes);
+    if (bytes) std::memcpy(img.data() + off, src, bytes);
+    return off;
+  };
+  q->off_imgs = append(imgs.data(), sizeof(DevImage) * imgs.size());
+  q->off_tile_img = append(tile_img.data(), sizeof(int32_t) * tile_img.size());
+  q->off_wg_tiles = q->has_wg_tiles ? append(wg_tiles.data(), sizeof(int32_t) * wg_tiles.size()) : 0;
   return RKLT_OK;
 }
 
-}  // namespace
-
-rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, const rklt_tuning* tuning,
-                             rklt_plan** out) {
-  clear_error();
-  if (!ctx || !imgs || !out || n < 1) return fail(RKLT_E_INVAL, "rklt_plan_create: NULL argument or n < 1");
-  *out = nullptr;
+// Validate `imgs`, group them by kernel class and build the plan's parts and
+// the host image of its work list.
+rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
+  rklt_ctx* ctx = p->ctx;
   int wg, bpt, grid_req;
-  rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
+  rklt_status st = check_tuning(p->has_tuning ? &p->tuning : nullptr, &wg, &bpt, &grid_req);
   if (st) return st;
   std::vector<DevImage> by_class[3];  // indexed by kernel class
-  std::vector<DevImage> dimgs_all;
+  std::vector<DevImage> all;
   int N = 0;
   bool dump = false;
   int64_t pixels = 0;
@@ -606,50 +599,133 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
       d.slot = k;
       dump = dump || imgs[k].coef_out || imgs[k].scaled_out;
       pixels += static_cast<int64_t>(imgs[k].H) * imgs[k].W;
-      dimgs_all.push_back(d);
+      all.push_back(d);
     }
     // a plan that dumps coefficients keeps every image on a dumping kernel
     for (int k = 0; k < n; ++k)
-      by_class[kernel_class(ctx->host[imgs[k].transform_id], imgs[k].level_shift, dump)].push_back(dimgs_all[k]);
+      by_class[kernel_class(ctx->host[imgs[k].transform_id], imgs[k].level_shift, dump)].push_back(all[k]);
   }
-  rklt_plan* p = new (std::nothrow) rklt_plan;
-  if (!p) return fail(RKLT_E_NOMEM, "rklt_plan_create: out of host memory");
-  p->ctx = ctx;
   p->N = N;
   p->dump = dump;
   p->n = n;
   p->pixels = pixels;
-  hipError_t e = use_device(ctx->device);
-  if (e != hipSuccess) {
-    delete p;
-    return hip_fail("hipSetDevice", e);
-  }
+  p->nparts = 0;
+  p->h_image.clear();
   for (int c = 2; c >= 0; --c) {
     if (by_class[c].empty()) continue;
-    st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts]);
-    if (st) {
-      for (int k = 0; k < p->nparts; ++k) free_part(p->parts[k]);
-      delete p;
-      return st;
-    }
+    st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts], p->h_image);
+    if (st) return st;
     ++p->nparts;
   }
+  return RKLT_OK;
+}
+
+rklt_status ensure_device_capacity(rklt_plan* p) {
+  const size_t need = p->h_image.size();
+  if (need <= p->d_cap) return RKLT_OK;
+  (void)hipFree(p->d_buf);
+  p->d_buf = nullptr;
+  p->d_cap = 0;
+  const size_t cap = need + need / 2 + 4096;
+  const hipError_t e = hipMalloc(&p->d_buf, cap);
+  if (e != hipSuccess) return fail(RKLT_E_NOMEM, "rklt_plan: hipMalloc of %zu bytes: %s", cap, hipGetErrorString(e));
+  p->d_cap = cap;
+  return RKLT_OK;
+}
+
+void destroy_plan(rklt_plan* p) {
+  (void)hipFree(p->d_buf);
+  if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+  delete p;
+}
+
+}  // namespace
+
+rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, const rklt_tuning* tuning,
+                             rklt_plan** out) {
+  clear_error();
+  if (!ctx || !imgs || !out || n < 1) return fail(RKLT_E_INVAL, "rklt_plan_create: NULL argument or n < 1");
+  *out = nullptr;
+  rklt_plan* p = new (std::nothrow) rklt_plan;
+  if (!p) return fail(RKLT_E_NOMEM, "rklt_plan_create: out of host memory");
+  p->ctx = ctx;
+  if (tuning) {
+    p->tuning = *tuning;
+    p->has_tuning = true;
+  }
+  rklt_status st = build_plan(p, imgs, n);
+  if (st) {
+    destroy_plan(p);
+    return st;
+  }
+  hipError_t e = use_device(ctx->device);
+  if (e != hipSuccess) {
+    destroy_plan(p);
+    return hip_fail("hipSetDevice", e);
+  }
+  if ((st = ensure_device_capacity(p))) {
+    destroy_plan(p);
+    return st;
+  }
+  e = hipMemcpy(p->d_buf, p->h_image.data(), p->h_image.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    destroy_plan(p);
+    return hip_fail("rklt_plan_create: hipMemcpy", e);
+  }
   *out = p;
+  return RKLT_OK;
+}
+
+rklt_status rklt_plan_update(rklt_plan* p, const rklt_image* imgs, int32_t n, void* stream) {
+  clear_error();
+  if (!p || !imgs || n < 1) return fail(RKLT_E_INVAL, "rklt_plan_update: NULL argument or n < 1");
+  rklt_status st = build_plan(p, imgs, n);
+  if (st) {
+    p->nparts = 0;  // a failed update leaves an empty plan
+    return st;
+  }
+  hipError_t e = use_device(p->ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  if ((st = ensure_device_capacity(p))) {
+    p->nparts = 0;
+    return st;
+  }
+  const size_t need = p->h_image.size();
+  if (need > p->h_cap) {
+    if (p->h_pinned) (void)hipHostFree(p->h_pinned);
+    p->h_pinned = nullptr;
+    p->h_cap = 0;
+    const size_t cap = need + need / 2 + 4096;
+    e = hipHostMalloc(&p->h_pinned, cap, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p->nparts = 0;
+      return fail(RKLT_E_NOMEM, "rklt_plan_update: hipHostMalloc of %zu bytes: %s", cap, hipGetErrorString(e));
+    }
+    p->h_cap = cap;
+  }
+  std::memcpy(p->h_pinned, p->h_image.data(), need);
+  e = hipMemcpyAsync(p->d_buf, p->h_pinned, need, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    p->nparts = 0;
+    return hip_fail("rklt_plan_update: hipMemcpyAsync", e);
+  }
   return RKLT_OK;
 }
 
 rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
   clear_error();
   if (!p || !d_res) return fail(RKLT_E_INVAL, "rklt_plan_run: NULL argument");
+  if (p->nparts == 0) return fail(RKLT_E_STATE, "rklt_plan_run: the plan holds no images (a failed update)");
   hipError_t e = use_device(p->ctx->device);
   if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  unsigned char* base = static_cast<unsigned char*>(p->d_buf);
   for (int k = 0; k < p->nparts; ++k) {
     const PlanPart& q = p->parts[k];
     KArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.imgs = q.d_imgs;
-    a.tile_img = q.d_tile_img;
-    a.wg_tiles = q.d_wg_tiles;
+    a.imgs = reinterpret_cast<const DevImage*>(base + q.off_imgs);
+    a.tile_img = reinterpret_cast<const int32_t*>(base + q.off_tile_img);
+    a.wg_tiles = q.has_wg_tiles ? reinterpret_cast<const int32_t*>(base + q.off_wg_tiles) : nullptr;
     a.tf = p->ctx->d_table;
     a.res = d_res;
     a.total_tiles = static_cast<int32_t>(q.total_tiles);
@@ -666,8 +742,7 @@ rklt_status rklt_plan_destroy(rklt_plan* p) {
   clear_error();
   if (!p) return fail(RKLT_E_INVAL, "rklt_plan_destroy: plan is NULL");
   (void)use_device(p->ctx->device);
-  for (int k = 0; k < p->nparts; ++k) free_part(p->parts[k]);
-  delete p;
+  destroy_plan(p);
   return RKLT_OK;
 }
 

@@ -91,6 +91,7 @@ def _load():
         "rklt_plan_info": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_copy_bytes": (st, [vp, vp, C.c_size_t, vp]),
         "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 3)]),
+        "rklt_plan_update": (st, [vp, C.POINTER(Image), C.c_int32, vp]),
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -104,7 +105,7 @@ _lib = _load()
 EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_create",
             "rklt_ctx_destroy", "rklt_ctx_add_transform", "rklt_codec", "rklt_plan_create",
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
-            "rklt_plan_launches", "rklt_ctx_transform_exact")
+            "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update")
 
 
 def lib():
@@ -277,7 +278,11 @@ class Plan:
                                      C.byref(tuning) if tuning is not None else None, C.byref(h)))
         self._h = h
         self.ctx = ctx
-        self.n = len(imgs)
+        self._refresh(len(imgs))
+
+    def _refresh(self, n: int):
+        h = self._h
+        self.n = n
         tiles, grid, pixels = C.c_int64(), C.c_int32(), C.c_int64()
         _check(_lib.rklt_plan_info(h, C.byref(tiles), C.byref(grid), C.byref(pixels)))
         self.tiles, self.grid, self.pixels = int(tiles.value), int(grid.value), int(pixels.value)
@@ -289,6 +294,12 @@ class Plan:
 
     def run(self, res_ptr: int, stream=None):
         _check(_lib.rklt_plan_run(self._h, C.c_void_p(res_ptr), C.c_void_p(_stream_handle(stream))))
+
+    def update(self, imgs: list[Image], stream=None):
+        """rklt_plan_update: new images, asynchronous upload on `stream`."""
+        arr = (Image * len(imgs))(*imgs)
+        _check(_lib.rklt_plan_update(self._h, arr, len(imgs), C.c_void_p(_stream_handle(stream))))
+        self._refresh(len(imgs))
 
     def close(self):
         if self._h:
