@@ -99,6 +99,44 @@ print(json.dumps({"seconds": dt, "pixels": px, "codings": n}))
                       f"(1024x1024, exact-rational reconstruction), {r['seconds']:.1f} s on one host thread"}
 
 
+SERVE_RATES = (200, 500, 1000, 2000, 5000)
+SERVE_POOL_RHOS = (0.1, 0.3, 0.5, 0.7, 0.9, 0.95)
+SERVE_POOL_SIDE = 8192
+SERVE_ARENA_BYTES = 4 << 30
+
+
+def _pool_image(k):
+    from paper_2111_14239_amd.inputs import ar1_image
+    return ar1_image(SERVE_POOL_SIDE, SERVE_POOL_SIDE, SERVE_POOL_RHOS[k], 7000 + k)
+
+
+def serving(ctx, seconds: float, streams: int) -> dict:
+    """Open-loop Poisson serving at each rate for `seconds` of arrivals (at
+    most 10^4 requests).  Requests are windows of pre-staged device images,
+    so no host-to-device copy of pixels is in the measurement."""
+    import torch
+
+    from paper_2111_14239_amd.inputs import serving_requests
+    from paper_2111_14239_amd.serve import Server, pool_requests
+
+    with ProcessPoolExecutor(max_workers=len(SERVE_POOL_RHOS)) as ex:
+        pool = [torch.from_numpy(a).to("cuda") for a in ex.map(_pool_image, range(len(SERVE_POOL_RHOS)))]
+    srv = Server(ctx, SERVE_ARENA_BYTES, streams=streams, max_batch=256)
+    out = []
+    for rate in SERVE_RATES:
+        count = max(1, min(10000, int(rate * seconds)))
+        reqs = pool_requests(serving_requests(float(rate), count), pool, list(SERVE_POOL_RHOS))
+        s = srv.serve(reqs)
+        out.append({"rate_per_s": rate, "requests": s["requests"], "rejected": s["rejected"],
+                    "p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+                    "throughput_mpix_s": s["throughput_mpix_s"], "mean_batch": s["mean_batch"]})
+    torch.cuda.synchronize()
+    return {"streams": streams, "arena_bytes": SERVE_ARENA_BYTES, "inputs": "pre-staged in device memory",
+            "requests": "Poisson arrivals, sides log-uniform in [256, 8192] (multiples of 8), "
+                        "rho U[0.1, 0.95], r U{1..64}, N=8, alpha=2; windows of six 8192x8192 AR(1) images",
+            "rates": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +148,9 @@ def main():
     ap.add_argument("--wg", type=int, default=0)
     ap.add_argument("--bpt", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="seconds of Poisson arrivals per serving rate (0 skips serving)")
+    ap.add_argument("--serve-streams", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -230,16 +271,19 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": KERNEL,
             "avg_launch_ms": avg_launch_ms,
         },
-        "latency_ms": {"p50": float(np.percentile(per_launch, 50)),
-                       "p99": float(np.percentile(per_launch, 99))},
+        "batch_launch_ms": {"p50": float(np.percentile(per_launch, 50)),
+                            "p99": float(np.percentile(per_launch, 99))},
         "plain": {"ms_per_step": plain_ms, "value": pixels / (plain_ms / 1e3) / 1e6,
                   "launches_per_step": n},
         "copy_ceiling_GBps": copy_gbs,
         "mean_psnr_db": float(np.mean([r["psnr_db"] for r in results if np.isfinite(r["psnr_db"])])),
     }
+    plan.close()
+    del src, dst
+    if args.serve_seconds > 0:
+        line["serving"] = serving(ctx, args.serve_seconds, args.serve_streams)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(specs)
-    plan.close()
     ctx.close()
     print(json.dumps(line), flush=True)
 

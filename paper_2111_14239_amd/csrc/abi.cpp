@@ -678,7 +678,11 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n, c
 
 rklt_status rklt_plan_update(rklt_plan* p, const rklt_image* imgs, int32_t n, void* stream) {
   clear_error();
-  if (!p || !imgs || n < 1) return fail(RKLT_E_INVAL, "rklt_plan_update: NULL argument or n < 1");
+  if (!p) return fail(RKLT_E_INVAL, "rklt_plan_update: plan is NULL");
+  if (!imgs || n < 1) {
+    p->nparts = 0;
+    return fail(RKLT_E_INVAL, "rklt_plan_update: imgs is NULL or n < 1");
+  }
   rklt_status st = build_plan(p, imgs, n);
   if (st) {
     p->nparts = 0;  // a failed update leaves an empty plan
