@@ -81,7 +81,7 @@ typedef struct {
   uint8_t* dst;         /* reconstruction (same geometry), or NULL: PSNR only    */
   int32_t* coef_out;    /* optional, verification: int32 B, H*W values          */
   float* scaled_out;    /* optional, verification: float B_hat, H*W values      */
-  int32_t H, W;         /* multiples of N, 1 <= H, W                             */
+  int32_t H, W;         /* multiples of N, 1 <= H, W; (H-1)*pitch + W < 2^31     */
   int32_t pitch_src;    /* >= W, multiple of 8 bytes                             */
   int32_t pitch_dst;    /* >= W, multiple of 8 bytes (ignored when dst is NULL)  */
   int32_t transform_id; /* from rklt_ctx_add_transform                           */

@@ -107,12 +107,18 @@ rklt_status check_image(rklt_ctx* ctx, const rklt_image& im, int index, DevImage
                 im.pitch_src, im.W);
   if (reinterpret_cast<uintptr_t>(im.src) % 8)
     return fail(RKLT_E_INVAL, "image %d: src is not 8-byte aligned", index);
+  // the kernels address an image with 32-bit byte offsets and mark missing
+  // blocks with offset 2^31, so an image must span less than 2^31 bytes
+  if (static_cast<int64_t>(im.H - 1) * im.pitch_src + im.W >= (int64_t{1} << 31))
+    return fail(RKLT_E_INVAL, "image %d: (H-1)*pitch_src+W spans 2^31 bytes or more", index);
   if (im.dst) {
     if (im.pitch_dst < im.W || im.pitch_dst % 8)
       return fail(RKLT_E_INVAL, "image %d: pitch_dst=%d must be >= W=%d and a multiple of 8", index,
                   im.pitch_dst, im.W);
     if (reinterpret_cast<uintptr_t>(im.dst) % 8)
       return fail(RKLT_E_INVAL, "image %d: dst is not 8-byte aligned", index);
+    if (static_cast<int64_t>(im.H - 1) * im.pitch_dst + im.W >= (int64_t{1} << 31))
+      return fail(RKLT_E_INVAL, "image %d: (H-1)*pitch_dst+W spans 2^31 bytes or more", index);
   }
   if (im.r < 1 || im.r > N * N)
     return fail(RKLT_E_INVAL, "image %d: r=%d outside 1..%d", index, im.r, N * N);
@@ -402,7 +408,9 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
           const int m = 4 * mu + 2 * hm + g / 2, n = 4 * (g % 2) + vm;
           if (dt.mfma == 1) {
             for (int e = 0; e < 8; ++e) {
-              const int o = order[8 * kappa + 4 * (lane >> 5) + e / 2];
+              // halves e = [hi v0, hi v1, lo v0, lo v1, hi v2, hi v3, lo v2, lo v3]
+              const int v = 2 * (e >> 2) + (e & 1);
+              const int o = order[8 * kappa + 4 * (lane >> 5) + v];
               const int i = o / 8, j = o % 8;
               dt.mV[mu][kappa][lane][e] = static_cast<_Float16>(static_cast<float>(dt.adj[m * 8 + i] * dt.adj[n * 8 + j]));
             }

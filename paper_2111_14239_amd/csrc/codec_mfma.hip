@@ -46,17 +46,51 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
+// The plan's work list is written before the launch and only read by the
+// kernel: constant-address-space reads become scalar loads that no pixel
+// store can invalidate.
+typedef const __attribute__((address_space(4))) DevImage* ConstImage;
+typedef const __attribute__((address_space(4))) int32_t* ConstInt;
+
+// Exact fp16 halves of four int32 coefficients (|B| < 32768): hi = B rounded
+// toward zero to fp16, lo = B - hi (|lo| < 16, an exact fp16 integer).  The
+// words are [hi0 hi1] [lo0 lo1] [hi2 hi3] [lo2 lo3]; lo comes from one
+// mixed-precision FMA per coefficient, lo = fma(hi, -1, B) rounded to fp16.
+__device__ __forceinline__ v8h split_fp16(int b0, int b1, int b2, int b3) {
+  const float f0 = static_cast<float>(b0), f1 = static_cast<float>(b1);
+  const float f2 = static_cast<float>(b2), f3 = static_cast<float>(b3);
+  v4u w;
+  w[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(f0, f1));
+  w[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(f2, f3));
+  uint32_t lo01, lo23;
+  // the trailing s_nop keeps two wait states between these VALU writes and a
+  // matrix instruction that reads them
+  asm("v_fma_mixlo_f16 %0, %2, -1.0, %4 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, %2, -1.0, %5 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixlo_f16 %1, %3, -1.0, %6 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %1, %3, -1.0, %7 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+      "s_nop 1"
+      : "=&v"(lo01), "=&v"(lo23)
+      : "v"(w[0]), "v"(w[2]), "v"(f0), "v"(f1), "v"(f2), "v"(f3));
+  w[1] = lo01;
+  w[3] = lo23;
+  return __builtin_bit_cast(v8h, w);
+}
+
 // One step: 32 blocks of one image.  px[c][rr] are pixel rows 4c + 2h + rr
 // (8 bytes each) of this lane's block; sF the forward operand (ranks >= r
-// zeroed) and sV the inverse operand, both in LDS.  Writes the reconstruction rows
-// to d (when non-null) and accumulates the squared-error terms.
+// zeroed) and sV the inverse operand, both in LDS.  Writes the
+// reconstruction rows through the buffer resource rd at lane offset od (rows
+// 4 mu + rr at pitch pd) and accumulates the squared-error terms of valid
+// blocks.
 template <int R8, int PATH>
 __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF, const void* sVraw, int lane,
-                                          float inv, float bias, uint8_t* d, int pd, bool valid, uint32_t& sxx,
-                                          uint32_t& sxy) {
+                                          float inv, float bias, __amdgpu_buffer_rsrc_t rd, uint32_t od, int pd,
+                                          bool valid, uint32_t& sxx, uint32_t& sxy) {
   v4i X[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -81,14 +115,8 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
 #pragma unroll
     for (int kappa = 0; kappa < R8; ++kappa) {
       const int g = kappa & 3;
-      v8h Bop;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float fb = static_cast<float>(acc[kappa >> 2][4 * g + v]);
-        const _Float16 hb = static_cast<_Float16>(fb);
-        Bop[2 * v] = hb;
-        Bop[2 * v + 1] = static_cast<_Float16>(fb - static_cast<float>(hb));
-      }
+      const v16i& A = acc[kappa >> 2];
+      const v8h Bop = split_fp16(A[4 * g], A[4 * g + 1], A[4 * g + 2], A[4 * g + 3]);
 #pragma unroll
       for (int mu = 0; mu < 2; ++mu)
         out[mu] = __builtin_amdgcn_mfma_f32_32x32x16_f16(sV[(mu * 8 + kappa) * 64 + lane], Bop, out[mu], 0, 0, 0);
@@ -124,15 +152,18 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
       for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(out[mu][4 * g + v], inv, bias), v, word);
       w[g] = word;
     }
+    // unconditional stores: lanes without a block carry an out-of-range
+    // offset and the buffer unit drops their writes
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
-      if (valid) {
-        if (d) {
-          u32x2 o;
-          o.x = w[2 * rr];
-          o.y = w[2 * rr + 1];
-          *as_global(reinterpret_cast<u32x2*>(d + static_cast<size_t>(rr) * pd + static_cast<size_t>(mu) * 4 * pd)) = o;
-        }
+      u32x2 o;
+      o.x = w[2 * rr];
+      o.y = w[2 * rr + 1];
+      __builtin_amdgcn_raw_buffer_store_b64(o, rd, od, (4 * mu + rr) * pd, 0);
+    }
+    if (valid) {
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
         sxx = __builtin_amdgcn_udot4(px[mu][rr].x, px[mu][rr].x, sxx, false);
         sxx = __builtin_amdgcn_udot4(px[mu][rr].y, px[mu][rr].y, sxx, false);
         sxx = __builtin_amdgcn_udot4(w[2 * rr], w[2 * rr], sxx, false);
@@ -144,55 +175,101 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
   }
 }
 
-// Pixel rows 4c + 2h + rr (c, rr in {0, 1}) of block b, or zeros.
-__device__ __forceinline__ void load_step(const DevImage* im, bool valid, int b, int bw, int ps, int h,
-                                          u32x2 (&px)[2][2]) {
-  if (valid) {
-    const int by = b / bw, bx = b - by * bw;
-    const uint8_t* s = im->src + (static_cast<size_t>(by) * 8 + 2 * h) * ps + bx * 8;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int rr = 0; rr < 2; ++rr)
-        px[c][rr] = *as_global(reinterpret_cast<const u32x2*>(s + static_cast<size_t>(4 * c + rr) * ps));
-  } else {
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int rr = 0; rr < 2; ++rr) px[c][rr] = u32x2{0u, 0u};
-  }
-}
+// Pixels and reconstructions go through raw buffer resources: a lane whose
+// block lies past the segment end gets this offset, which is beyond every
+// image (the host keeps image spans below 2^31 bytes), so its loads return
+// zero and its stores are dropped without a branch.  Every step then issues
+// the same memory operations on every path, which keeps the wait counts of
+// the prefetch ring exact.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+constexpr int kRawBufferFlags = 0x00020000;
+
+// Wave-uniform fields of the image a segment codes (held in SGPRs).
+struct SegImage {
+  __amdgpu_buffer_rsrc_t rs, rd;
+  int ps, pd, bw;
+};
+
+// Block row and column of the first block of a wave's step, wave-uniform:
+// a step covers 32 consecutive blocks in raster order and the next step of
+// the same wave starts `stride` blocks later.
+struct Cursor {
+  int by, bx;
+};
 
 // Steps [base0, be) of one image segment, 32 blocks per step, strided by
 // the workgroup's waves.  A ring of RKLT_MFMA_RING pixel buffers keeps the
-// loads of the next steps in flight while a step is computed.
-template <int R8, int PATH>
-__device__ __forceinline__ void segment(const DevImage* im, int base0, int be, int stride, const v4i* sF,
+// loads of the next steps in flight while a step is computed.  WIDE images
+// (at least 32 blocks per row) find each lane's block from a wave-uniform
+// cursor: the 32 blocks of a step wrap to the next block row at most once,
+// so a lane's offset is the cursor's offset plus one of two lane offsets.
+// Narrower images divide per lane.
+template <int R8, int PATH, bool WIDE>
+__device__ __forceinline__ void segment(const SegImage& im, int base0, int be, int stride, const v4i* sF,
                                         const void* sV, int lane, int q, int h, float inv, float bias,
                                         uint32_t& sxx, uint32_t& sxy) {
-  const int bw = im->bw, ps = im->ps, pd = im->pd;
-  uint8_t* const dst = im->dst;
+  const int bw = im.bw, ps = im.ps, pd = im.pd;
+  const uint32_t Ls = 8u * q + 2u * h * ps, Ld = 8u * q + 2u * h * pd;
+  const uint32_t Ws = 8u * (ps - bw), Wd = 8u * (pd - bw);
+  // byte offset of this lane's block of step `base` (cursor c) from the image
+  // start, rows 2h and up; out of range for lanes past the segment end
+  auto offset = [&](const Cursor& c, int base, int pitch, uint32_t L, uint32_t Wr) -> uint32_t {
+    uint32_t off;
+    if (WIDE) {
+      off = static_cast<uint32_t>(c.by * 8 * pitch + c.bx * 8) + L + (q >= bw - c.bx ? Wr : 0u);
+    } else {
+      const int b = base + q;
+      const int by = b / bw, bx = b - by * bw;
+      off = static_cast<uint32_t>(by * 8 + 2 * h) * pitch + static_cast<uint32_t>(bx) * 8;
+    }
+    return q < be - base ? off : kOutOfRange;
+  };
+  auto advance = [&](Cursor& c) {
+    if (WIDE) {
+      c.bx += stride;
+      while (c.bx >= bw) {
+        c.bx -= bw;
+        ++c.by;
+      }
+    }
+  };
+  // pixel rows 4c + 2h + rr of this lane's block of step `base`
+  auto load = [&](u32x2 (&px)[2][2], const Cursor& c, int base) {
+    const uint32_t off = offset(c, base, ps, Ls, Ws);
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr)
+        px[cc][rr] = __builtin_amdgcn_raw_buffer_load_b64(im.rs, off, (4 * cc + rr) * ps, 0);
+  };
+  Cursor cl{0, 0};
+  if (WIDE) {
+    cl.by = base0 / bw;
+    cl.bx = base0 - cl.by * bw;
+  }
+  Cursor cs = cl;
 #if RKLT_MFMA_RING == 3
   u32x2 p0[2][2], p1[2][2], p2[2][2];
-  load_step(im, base0 + q < be, base0 + q, bw, ps, h, p0);
-  load_step(im, base0 + stride + q < be, base0 + stride + q, bw, ps, h, p1);
-  load_step(im, base0 + 2 * stride + q < be, base0 + 2 * stride + q, bw, ps, h, p2);
+  load(p0, cl, base0);
+  advance(cl);
+  load(p1, cl, base0 + stride);
+  advance(cl);
+  load(p2, cl, base0 + 2 * stride);
+  advance(cl);
 #else
   u32x2 p0[2][2], p1[2][2];
-  load_step(im, base0 + q < be, base0 + q, bw, ps, h, p0);
-  load_step(im, base0 + stride + q < be, base0 + stride + q, bw, ps, h, p1);
+  load(p0, cl, base0);
+  advance(cl);
+  load(p1, cl, base0 + stride);
+  advance(cl);
 #endif
   auto run = [&](u32x2 (&px)[2][2], int base) {
-    const int b = base + q;
-    const bool valid = b < be;
-    uint8_t* d = nullptr;
-    if (valid && dst) {
-      const int by = b / bw, bx = b - by * bw;
-      d = dst + (static_cast<size_t>(by) * 8 + 2 * h) * pd + bx * 8;
-    }
-    mfma_step<R8, PATH>(px, sF, sV, lane, inv, bias, d, pd, valid, sxx, sxy);
-    const int nb = b + RKLT_MFMA_RING * stride;
-    load_step(im, nb < be, nb, bw, ps, h, px);
+    const bool valid = q < be - base;
+    const uint32_t od = offset(cs, base, pd, Ld, Wd);
+    mfma_step<R8, PATH>(px, sF, sV, lane, inv, bias, im.rd, od, pd, valid, sxx, sxy);
+    advance(cs);
+    load(px, cl, base + RKLT_MFMA_RING * stride);
+    advance(cl);
   };
   for (int base = base0; base < be; base += RKLT_MFMA_RING * stride) {
     run(p0, base);
@@ -203,6 +280,14 @@ __device__ __forceinline__ void segment(const DevImage* im, int base0, int be, i
     run(p2, base + 2 * stride);
 #endif
   }
+}
+
+template <int R8, int PATH>
+__device__ __forceinline__ void segment_any(const SegImage& im, int base0, int be, int stride, const v4i* sF,
+                                            const void* sV, int lane, int q, int h, float inv, float bias,
+                                            uint32_t& sxx, uint32_t& sxy) {
+  if (im.bw >= 32) segment<R8, PATH, true>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
+  else segment<R8, PATH, false>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
 }
 
 // PLAN: a batch plan's work list; otherwise the plain path's single image.
@@ -219,17 +304,22 @@ void rklt_mfma8_kernel(KArgs a) {
   __shared__ unsigned long long red[4];
   __shared__ uint4 sV[2 * 8 * 64];  // inverse operand of the current transform (16 KB)
   __shared__ v4i sF[2 * 2 * 64];  // forward operand of the current (transform, r) (4 KB)
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // the wave index is wave-uniform; saying so keeps every per-step block
+  // cursor in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   const int nwaves = static_cast<int>(blockDim.x >> 6);
   const int q = lane & 31, h = lane >> 5;
   const int stride = nwaves * 32;
   int loaded = -1, loaded_r = -1;
+  const ConstInt wg_tiles = (ConstInt)(a.wg_tiles);
+  const ConstInt tile_img = (ConstInt)(a.tile_img);
   // contiguous tile range of this workgroup: cost-balanced by the plan, or an
   // equal share of the tiles
-  const int t_end = PLAN && a.wg_tiles ? a.wg_tiles[blockIdx.x + 1] : tile_end_of(a.total_tiles);
-  for (int t = PLAN && a.wg_tiles ? a.wg_tiles[blockIdx.x] : tile_begin(a.total_tiles); t < t_end;) {
-    const int ii = PLAN ? __builtin_amdgcn_readfirstlane(a.tile_img[t]) : 0;
-    const DevImage* im = PLAN ? a.imgs + ii : &a.one;
+  const int t_end = PLAN && a.wg_tiles ? wg_tiles[blockIdx.x + 1] : tile_end_of(a.total_tiles);
+  for (int t = PLAN && a.wg_tiles ? wg_tiles[blockIdx.x] : tile_begin(a.total_tiles); t < t_end;) {
+    const int ii = PLAN ? __builtin_amdgcn_readfirstlane(tile_img[t]) : 0;
+    const ConstImage im = PLAN ? (ConstImage)(a.imgs + ii) : (ConstImage)(&a.one);
     const int tile0 = im->tile0, ntiles = im->ntiles;
     const int seg_end = tile0 + ntiles < t_end ? tile0 + ntiles : t_end;
     const int tid = __builtin_amdgcn_readfirstlane(im->tid);
@@ -259,19 +349,31 @@ void rklt_mfma8_kernel(KArgs a) {
     const int tb = im->tile_blocks, nblocks = im->nblocks;
     const int bs = (t - tile0) * tb;
     const int be = (seg_end - tile0) * tb < nblocks ? (seg_end - tile0) * tb : nblocks;
+    SegImage si;
+    si.ps = __builtin_amdgcn_readfirstlane(im->ps);
+    si.pd = __builtin_amdgcn_readfirstlane(im->pd);
+    si.bw = __builtin_amdgcn_readfirstlane(im->bw);
+    {
+      const int H = __builtin_amdgcn_readfirstlane(im->H), W = __builtin_amdgcn_readfirstlane(im->W);
+      uint8_t* const dst = im->dst;
+      si.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(im->src), 0, (H - 1) * si.ps + W,
+                                                kRawBufferFlags);
+      // no reconstruction wanted: an empty range drops every store
+      si.rd = __builtin_amdgcn_make_buffer_rsrc(dst, 0, dst ? (H - 1) * si.pd + W : 0, kRawBufferFlags);
+    }
     uint32_t sxx = 0, sxy = 0;
     const int base0 = bs + wave * 32;
     const int path = __builtin_amdgcn_readfirstlane(tf->mfma);
-#define RKLT_SEG(RR)                                                                        \
-  case RR:                                                                                  \
-    if (path == 1) segment<RR, 1>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); \
-    else segment<RR, 2>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);           \
+#define RKLT_SEG(RR)                                                                                   \
+  case RR:                                                                                             \
+    if (path == 1) segment_any<RR, 1>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); \
+    else segment_any<RR, 2>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);           \
     break;
     switch (R8) {
       RKLT_SEG(1) RKLT_SEG(2) RKLT_SEG(3) RKLT_SEG(4) RKLT_SEG(5) RKLT_SEG(6) RKLT_SEG(7)
       default:
-        if (path == 1) segment<8, 1>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
-        else segment<8, 2>(im, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
+        if (path == 1) segment_any<8, 1>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
+        else segment_any<8, 2>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
         break;
     }
 #undef RKLT_SEG

@@ -47,7 +47,9 @@ struct alignas(256) DevTransform {
   //                        pixel of K-chunk c; value T[i][m] T[j][n]
   //   mV[mu][kappa][lane]  inverse A operand of v_mfma_f32_32x32x16_f16, 8 halves:
   //                        row = pixel of chunk mu, K = (rank, hi/lo part) of
-  //                        coefficient chunk kappa; value adj[m][i] adj[n][j]
+  //                        coefficient chunk kappa, halves ordered hi v0, hi v1,
+  //                        lo v0, lo v1, hi v2, hi v3, lo v2, lo v3 for the
+  //                        ranks 8 kappa + 4 (lane / 32) + v; value adj[m][i] adj[n][j]
   //   mVf[mu][kappa][v][lane] inverse A operand of v_mfma_f32_32x32x2_f32 for
   //                        transforms without a small exact inverse (exact =
   //                        0): row = pixel, K = lane / 32 selects rank
