@@ -189,22 +189,30 @@ def main():
     for _ in range(args.warmup):
         plan.run(int(res.data_ptr()), stream)
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    # timed region: K back-to-back launches between two events on the
+    # launch stream (an event between launches serialises the queue and adds
+    # its own flush, so per-launch events are kept out of the throughput)
     t_all0 = torch.cuda.Event(enable_timing=True)
     t_all1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_all0.record(stream)
-    for k in range(args.steps):
-        starts[k].record(stream)
+    for _ in range(args.steps):
         plan.run(int(res.data_ptr()), stream)
-        ends[k].record(stream)
     t_all1.record(stream)
     torch.cuda.synchronize()
     ms_total = t_all0.elapsed_time(t_all1)
-    per_launch = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
     ms_per_step = ms_total / args.steps
-    avg_launch_ms = float(per_launch.mean())
+    avg_launch_ms = ms_per_step
+    # launch latency: each launch alone between its own events
+    n_lat = min(args.steps, 100)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(n_lat)]
+    for k in range(n_lat):
+        starts[k].record(stream)
+        plan.run(int(res.data_ptr()), stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    per_launch = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
     results = rklt.read_results(res)
     assert all(r["tiles"] > 0 for r in results)
 

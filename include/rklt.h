@@ -161,6 +161,18 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
  * 1e-3 of a rounding tie.  Errors: E_INVAL (NULL ctx, unknown id). */
 rklt_status rklt_ctx_transform_exact(rklt_ctx* ctx, int32_t id, int32_t* exact, int64_t* den);
 
+/* Inverse form the N = 8 matrix-core kernel (level shift 128, the batched
+ * path's usual kernel) uses for transform `id` with r kept coefficients:
+ *   *form = 1  exact, one fp16 pass (every partial sum below 2^24);
+ *           3  exact, fp16 with separate accumulators for the high and low
+ *              parts of each coefficient;
+ *           2  FP32 (no exact inverse, or its bounds do not hold): a pixel may
+ *              differ by one level where x is within about 1e-3 of a tie;
+ *           0  the transform does not run on the matrix-core kernel.
+ * Exact forms give floor(x + 1/2) of the exact rational x, ties included.
+ * Errors: E_INVAL (NULL ctx or form, unknown id, r outside 1..N*N). */
+rklt_status rklt_ctx_mfma_form(rklt_ctx* ctx, int32_t id, int32_t r, int32_t* form);
+
 /* ---- codec -------------------------------------------------------------- */
 
 /* Plain path: code one image with one kernel launch on `stream` (§4.1).

@@ -75,7 +75,7 @@ bool block8_fits(const DevTransform& t, int ell) {
 
 int kernel_class(const DevTransform& t, int ell, bool dump) {
   if (!block8_fits(t, ell)) return 0;
-  return (t.mfma && !dump) ? 2 : 1;
+  return (t.m_ok && !dump) ? 2 : 1;
 }
 
 hipError_t use_device(int device) {
@@ -369,13 +369,22 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
   }
   if (N == 8 && max_abs * max_abs <= 127) {
     // Matrix-core operands.  The forward weights T_im T_jn fit int8.  The
-    // inverse takes one of two forms (DevTransform::mfma):
-    //   1  exact, fp16: needs an exact inverse with |B| <= 32768 (so that
-    //      B = hi + lo, hi = fp16(B), |lo| <= 8, both exact in fp16), weights
-    //      adj_mi adj_nj exact fp16 integers (|.| <= 2048) and every partial
-    //      sum below 2^24, bounded by sum_ij |adj_mi adj_nj| (Bmax_ij + 16);
-    //   2  FP32 (v_mfma_f32_32x32x2_f32) with the weights that match the
-    //      epilogue constants: adj (x) adj when exact, else T^-1 (x) T^-1.
+    // inverse weights of output pixel (m, n) against coefficient k = (i, j)
+    // are w = adj_mi adj_nj (exact inverse T^-1 = adj / den), and
+    // |B_k| <= Bmax_k = 128 L1_i L1_j.  Per (transform, r) the kernel takes
+    //   1  one fp16 pass, B = hi + lo with hi = B rounded toward zero to fp16
+    //      and |lo| < 16 (needs |B| < 32768): exact when every partial sum,
+    //      at most S_r = sum_{k<r} |w_k| (Bmax_k + 16), stays below 2^24;
+    //      m_r1 is the largest such r;
+    //   3  two accumulators, hi = B rounded to a multiple of 64 and lo = B - hi
+    //      (|lo| <= 32): the hi sums are multiples of 64 below 2^30 and the lo
+    //      sums below 2^24, so both are exact, and so is their sum Out when
+    //      |Out| < 2^24.  Out = den^2 (A - 128) minus the dropped terms, so
+    //      |Out| <= min(P_r, 128 den^2 + P_64 - P_r), P_r = sum_{k<r} |w_k| Bmax_k;
+    //   2  FP32 (v_mfma_f32_32x32x2_f32) otherwise.
+    // The weights must be exact fp16 integers (|w| <= 2048) for forms 1 and 3,
+    // and the epilogue's rounding argument needs delta > 8e-5 (as for the
+    // register kernel).
     int32_t order[64];
     zigzag(8, order);
     fill_forward_operand(t->T, order, dt.mF);
@@ -384,21 +393,50 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
       L1[i] = 0;
       for (int j = 0; j < 8; ++j) L1[i] += std::abs(t->T[i * 8 + j]);
     }
-    bool ok = dt.exact != 0;
-    double omax = 0;
-    for (int m = 0; m < 8 && ok; ++m)
-      for (int n = 0; n < 8 && ok; ++n) {
-        double o = 0;
-        for (int i = 0; i < 8; ++i)
-          for (int j = 0; j < 8; ++j) {
-            const double w = std::fabs(static_cast<double>(dt.adj[m * 8 + i]) * dt.adj[n * 8 + j]);
+    int64_t madj[64], mden = 0;
+    bool mex = exact_inverse(8, t->T, madj, &mden);
+    double d2 = 0, delta = 0;
+    if (mex) {
+      d2 = static_cast<double>(mden) * static_cast<double>(mden);
+      delta = (mden % 2 == 0) ? 0.5 / d2 : 0.25 / d2;
+      mex = delta > 8e-5;
+    }
+    bool wfit = mex;  // weights exact in fp16 and |B| < 32768
+    for (int k = 0; k < 64 && wfit; ++k) {
+      const int i = order[k] / 8, j = order[k] % 8;
+      if (128.0 * L1[i] * L1[j] >= 32768.0) wfit = false;
+      for (int m = 0; m < 8 && wfit; ++m)
+        if (std::llabs(madj[m * 8 + i]) * std::llabs(madj[m * 8 + j]) > 2048) wfit = false;
+    }
+    // largest r for form 1, and form 3's bounds, over every output pixel
+    int r1 = wfit ? 64 : 0;
+    bool path3 = wfit;
+    if (wfit) {
+      for (int m = 0; m < 8; ++m)
+        for (int n = 0; n < 8; ++n) {
+          double S = 0, P[65], hi = 0, lo = 0;
+          P[0] = 0;
+          for (int k = 0; k < 64; ++k) {
+            const int i = order[k] / 8, j = order[k] % 8;
+            const double w = std::fabs(static_cast<double>(madj[m * 8 + i]) * static_cast<double>(madj[n * 8 + j]));
             const double bmax = 128.0 * L1[i] * L1[j];
-            if (w > 2048.0 || bmax > 32768.0) ok = false;
-            o += w * (bmax + 16.0);
+            S += w * (bmax + 16.0);
+            if (S >= 16777216.0 && k < r1) r1 = k;  // r = k + 1 coefficients break the bound
+            P[k + 1] = P[k] + w * bmax;
+            hi += w * (bmax + 32.0);
+            lo += w * 32.0;
           }
-        omax = std::fmax(omax, o);
-      }
-    dt.mfma = (ok && omax < 16777216.0) ? 1 : 2;
+          if (hi >= 1073741824.0 || lo >= 16777216.0) path3 = false;
+          for (int r = 1; r <= 64 && path3; ++r)
+            if (std::fmin(P[r], 128.0 * d2 + P[64] - P[r]) >= 16777216.0) path3 = false;
+        }
+    }
+    dt.m_ok = 1;
+    dt.m_r1 = r1;
+    dt.m_path3 = path3 ? 1 : 0;
+    dt.m_den = mex ? static_cast<int32_t>(mden) : 0;
+    dt.m_inv = mex ? static_cast<float>(1.0 / d2) : 1.0f;
+    dt.m_bias = mex ? static_cast<float>(128.0 + delta) : 128.0f + 1.0f / 4096.0f;
     for (int mu = 0; mu < 2; ++mu)
       for (int kappa = 0; kappa < 8; ++kappa)
         for (int lane = 0; lane < 64; ++lane) {
@@ -406,22 +444,21 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
           const int M = lane & 31;
           const int g = M >> 3, hm = (M >> 2) & 1, vm = M & 3;
           const int m = 4 * mu + 2 * hm + g / 2, n = 4 * (g % 2) + vm;
-          if (dt.mfma == 1) {
+          if (wfit) {
             for (int e = 0; e < 8; ++e) {
               // halves e = [hi v0, hi v1, lo v0, lo v1, hi v2, hi v3, lo v2, lo v3]
               const int v = 2 * (e >> 2) + (e & 1);
               const int o = order[8 * kappa + 4 * (lane >> 5) + v];
               const int i = o / 8, j = o % 8;
-              dt.mV[mu][kappa][lane][e] = static_cast<_Float16>(static_cast<float>(dt.adj[m * 8 + i] * dt.adj[n * 8 + j]));
+              dt.mV[mu][kappa][lane][e] = static_cast<_Float16>(static_cast<float>(madj[m * 8 + i] * madj[n * 8 + j]));
             }
-          } else {
-            for (int v = 0; v < 4; ++v) {
-              const int o = order[8 * kappa + 4 * (lane >> 5) + v];
-              const int i = o / 8, j = o % 8;
-              const double w = dt.exact ? static_cast<double>(dt.adj[m * 8 + i]) * dt.adj[n * 8 + j]
-                                        : static_cast<double>(t->G[m * 8 + i]) * t->s[i] * t->G[n * 8 + j] * t->s[j];
-              dt.mVf[mu][kappa][v][lane] = static_cast<float>(w);
-            }
+          }
+          for (int v = 0; v < 4; ++v) {
+            const int o = order[8 * kappa + 4 * (lane >> 5) + v];
+            const int i = o / 8, j = o % 8;
+            const double w = mex ? static_cast<double>(madj[m * 8 + i]) * static_cast<double>(madj[n * 8 + j])
+                                 : static_cast<double>(t->G[m * 8 + i]) * t->s[i] * t->G[n * 8 + j] * t->s[j];
+            dt.mVf[mu][kappa][v][lane] = static_cast<float>(w);
           }
         }
   }
@@ -507,7 +544,7 @@ namespace {
 // eight 32x32x2 products per chunk).
 double mfma8_block_cost(int path, int r) {
   const int R8 = (r + 7) / 8;
-  return path == 1 ? 0.0760 + 0.0030 * R8 : 0.0626 + 0.0182 * R8;
+  return path == 1 ? 0.0760 + 0.0030 * R8 : path == 3 ? 0.0760 + 0.0080 * R8 : 0.0626 + 0.0182 * R8;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -554,7 +591,7 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
     std::vector<double> cost(static_cast<size_t>(total));
     double sum = 0;
     for (size_t k = 0; k < imgs.size(); ++k) {
-      const double c = mfma8_block_cost(ctx->host[imgs[k].tid].mfma, imgs[k].r);
+      const double c = mfma8_block_cost(mfma8_path(ctx->host[imgs[k].tid], imgs[k].r), imgs[k].r);
       for (int t = 0; t < imgs[k].ntiles; ++t) {
         const int64_t b0 = static_cast<int64_t>(t) * imgs[k].tile_blocks;
         const int64_t nb = std::min<int64_t>(imgs[k].tile_blocks, imgs[k].nblocks - b0);
@@ -792,6 +829,18 @@ rklt_status rklt_ctx_transform_exact(rklt_ctx* ctx, int32_t id, int32_t* exact, 
     return fail(RKLT_E_INVAL, "rklt_ctx_transform_exact: unknown transform id %d", id);
   if (exact) *exact = ctx->host[id].exact;
   if (den) *den = ctx->host[id].den;
+  return RKLT_OK;
+}
+
+rklt_status rklt_ctx_mfma_form(rklt_ctx* ctx, int32_t id, int32_t r, int32_t* form) {
+  clear_error();
+  if (!ctx || !form) return fail(RKLT_E_INVAL, "rklt_ctx_mfma_form: NULL argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (id < 0 || id >= static_cast<int>(ctx->host.size()))
+    return fail(RKLT_E_INVAL, "rklt_ctx_mfma_form: unknown transform id %d", id);
+  const DevTransform& t = ctx->host[id];
+  if (r < 1 || r > t.N * t.N) return fail(RKLT_E_INVAL, "rklt_ctx_mfma_form: r=%d outside 1..%d", r, t.N * t.N);
+  *form = t.m_ok ? mfma8_path(t, r) : 0;
   return RKLT_OK;
 }
 

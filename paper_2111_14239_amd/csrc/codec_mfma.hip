@@ -1,22 +1,25 @@
 // Matrix-core kernel of the N = 8 codec (level shift 128, int8-range T): the
 // same computation as the register kernel, with both 2D transforms as
 // products over the 64 pixels of a block:
-//   forward   vec(B)  = (T (x) T) vec(A - 128)            v_mfma_i32_32x32x32_i8
-//   inverse   vec(Out) = (adj (x) adj) vec(mask (.) B)      v_mfma_f32_32x32x16_f16
-// (transforms without a small exact inverse take the FP32 form
-//   vec(A' - 128) = (T^-1 (x) T^-1) vec(mask (.) B)        v_mfma_f32_32x32x2_f32
-// with FP32 accuracy, like the register kernel's fallback)
-// where (x) is the Kronecker product (so B = T (A - 128) T^T, exact int32) and
-// Out = adj (mask (.) B) adj^T = den^2 (A' - 128) as in the register kernel.
+//   forward   vec(B)   = (T (x) T) vec(A - 128)           v_mfma_i32_32x32x32_i8
+//   inverse   vec(Out) = (adj (x) adj) vec(mask (.) B)    v_mfma_f32_32x32x16_f16
+// where (x) is the Kronecker product (so B = T (A - 128) T^T, exact int32),
+// T^-1 = adj / den and Out = den^2 (A' - 128) as in the register kernel.
 //
 // A wave codes 32 blocks per step: block = lane % 32.  The forward product
 // takes 32 zig-zag ranks per instruction pair (two K-chunks of 32 pixels);
 // rows of ranks >= r are zeroed in the operand, so truncation costs nothing
-// and only ceil(r / 8) coefficient chunks enter the inverse.  Each coefficient
-// enters the fp16 inverse as two exact halves B = hi + lo (hi = B rounded to
-// fp16, |B| <= 8192 so |lo| <= 4); weights are integers |adj adj| <= 2048 and
-// every partial sum stays below 2^24 (checked on the host), so the FP32
-// accumulation is exact and Out is the exact integer.
+// and only ceil(r / 8) coefficient chunks enter the inverse.  The inverse of
+// an image takes one of three forms, chosen on the host per (transform, r):
+//   1  each coefficient enters as two exact fp16 halves B = hi + lo (hi = B
+//      rounded toward zero, |lo| < 16); the weights are integers
+//      |adj adj| <= 2048 and every partial sum stays below 2^24, so the FP32
+//      accumulation is exact and Out is the exact integer;
+//   3  hi = B rounded to a multiple of 64 and lo = B - hi go to separate
+//      accumulators (the hi sums are multiples of 64 below 2^30, the lo sums
+//      small), and their sum is exact because |Out| < 2^24 is certified;
+//   2  no exact inverse fits: vec(A' - 128) in FP32 with
+//      v_mfma_f32_32x32x2_f32, like the register kernel's fallback.
 //
 // Operand layouts (checked on gfx950 with a lane-layout probe): A lane l holds
 // row l % 32 and K elements 16 (l / 32) + e (int8) or 8 (l / 32) + e (fp16);
@@ -42,6 +45,16 @@ namespace {
 #endif
 #ifndef RKLT_MFMA_RING
 #define RKLT_MFMA_RING 3
+#endif
+// Cache-policy bits of the pixel loads and reconstruction stores.  The
+// reconstruction is written once and not read again by the kernel:
+// non-temporal stores (bit 1) keep it from lingering dirty in L2, which
+// otherwise costs a write-back at the end of every launch.
+#ifndef RKLT_MFMA_LOAD_AUX
+#define RKLT_MFMA_LOAD_AUX 0
+#endif
+#ifndef RKLT_MFMA_STORE_AUX
+#define RKLT_MFMA_STORE_AUX 2
 #endif
 
 typedef int v4i __attribute__((ext_vector_type(4)));
@@ -81,12 +94,31 @@ __device__ __forceinline__ v8h split_fp16(int b0, int b1, int b2, int b3) {
   return __builtin_bit_cast(v8h, w);
 }
 
+// Exact fp16 halves of four int32 coefficients for the two-accumulator
+// inverse: hi = B rounded to a multiple of 64 (exact in fp16 for |B| < 65504),
+// lo = B - hi in [-32, 31].  Bh holds the hi parts in the hi slots of the
+// operand layout and zeros in the lo slots; Bl the reverse.
+__device__ __forceinline__ void split_fp16_64(int b0, int b1, int b2, int b3, v8h& Bh, v8h& Bl) {
+  const int h0 = (b0 + 32) & ~63, h1 = (b1 + 32) & ~63, h2 = (b2 + 32) & ~63, h3 = (b3 + 32) & ~63;
+  v4u wh, wl;
+  wh[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(static_cast<float>(h0), static_cast<float>(h1)));
+  wh[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(static_cast<float>(h2), static_cast<float>(h3)));
+  wl[1] = __builtin_bit_cast(uint32_t,
+                             __builtin_amdgcn_cvt_pkrtz(static_cast<float>(b0 - h0), static_cast<float>(b1 - h1)));
+  wl[3] = __builtin_bit_cast(uint32_t,
+                             __builtin_amdgcn_cvt_pkrtz(static_cast<float>(b2 - h2), static_cast<float>(b3 - h3)));
+  wh[1] = wh[3] = 0u;
+  wl[0] = wl[2] = 0u;
+  Bh = __builtin_bit_cast(v8h, wh);
+  Bl = __builtin_bit_cast(v8h, wl);
+}
+
 // One step: 32 blocks of one image.  px[c][rr] are pixel rows 4c + 2h + rr
 // (8 bytes each) of this lane's block; sF the forward operand (ranks >= r
 // zeroed) and sV the inverse operand, both in LDS.  Writes the
 // reconstruction rows through the buffer resource rd at lane offset od (rows
 // 4 mu + rr at pitch pd) and accumulates the squared-error terms of valid
-// blocks.
+// blocks.  PATH is the inverse form (1 and 3 exact, 2 FP32).
 template <int R8, int PATH>
 __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF, const void* sVraw, int lane,
                                           float inv, float bias, __amdgpu_buffer_rsrc_t rd, uint32_t od, int pd,
@@ -99,19 +131,54 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
     X[c][2] = static_cast<int>(px[c][1].x ^ 0x80808080u);
     X[c][3] = static_cast<int>(px[c][1].y ^ 0x80808080u);
   }
-  const v16i zi = {};
   v16i acc[2];
-  acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(0 * 2 + 0) * 64 + lane], X[0], zi, 0, 0, 0);
-  acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(0 * 2 + 1) * 64 + lane], X[1], acc[0], 0, 0, 0);
-  if (R8 > 4) {
-    acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(1 * 2 + 0) * 64 + lane], X[0], zi, 0, 0, 0);
-    acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(1 * 2 + 1) * 64 + lane], X[1], acc[1], 0, 0, 0);
-  }
+  auto forward = [&]() {
+    const v16i zi = {};
+    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(0 * 2 + 0) * 64 + lane], X[0], zi, 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(0 * 2 + 1) * 64 + lane], X[1], acc[0], 0, 0, 0);
+    if (R8 > 4) {
+      acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(1 * 2 + 0) * 64 + lane], X[0], zi, 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sF[(1 * 2 + 1) * 64 + lane], X[1], acc[1], 0, 0, 0);
+    }
+  };
+  if (PATH != 3) forward();
+  // Reconstruction of pixel chunk mu: register 4g + v is pixel row
+  // 4 mu + 2h + g / 2, column 4 (g % 2) + v of this lane's block.
+  auto finish = [&](const v16f& o, int mu) {
+    uint32_t w[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(o[4 * g + v], inv, bias), v, word);
+      w[g] = word;
+    }
+    // unconditional stores: lanes without a block carry an out-of-range
+    // offset and the buffer unit drops their writes
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      u32x2 ow;
+      ow.x = w[2 * rr];
+      ow.y = w[2 * rr + 1];
+      __builtin_amdgcn_raw_buffer_store_b64(ow, rd, od, (4 * mu + rr) * pd, RKLT_MFMA_STORE_AUX);
+    }
+    if (valid) {
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) {
+        sxx = __builtin_amdgcn_udot4(px[mu][rr].x, px[mu][rr].x, sxx, false);
+        sxx = __builtin_amdgcn_udot4(px[mu][rr].y, px[mu][rr].y, sxx, false);
+        sxx = __builtin_amdgcn_udot4(w[2 * rr], w[2 * rr], sxx, false);
+        sxx = __builtin_amdgcn_udot4(w[2 * rr + 1], w[2 * rr + 1], sxx, false);
+        sxy = __builtin_amdgcn_udot4(px[mu][rr].x, w[2 * rr], sxy, false);
+        sxy = __builtin_amdgcn_udot4(px[mu][rr].y, w[2 * rr + 1], sxy, false);
+      }
+    }
+  };
   const v16f zf = {};
-  v16f out[2] = {zf, zf};
   if (PATH == 1) {
     // exact fp16 inverse: each coefficient as two exact halves B = hi + lo
     const v8h* sV = static_cast<const v8h*>(sVraw);
+    v16f out[2] = {zf, zf};
 #pragma unroll
     for (int kappa = 0; kappa < R8; ++kappa) {
       const int g = kappa & 3;
@@ -123,9 +190,38 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
       // keep each chunk's operand reads next to its use (register pressure)
       __builtin_amdgcn_sched_barrier(0);
     }
+    finish(out[0], 0);
+    finish(out[1], 1);
+  } else if (PATH == 3) {
+    // exact fp16 inverse with the hi parts (multiples of 64) and the lo parts
+    // summed in separate accumulators, one pixel chunk at a time; the forward
+    // product is recomputed per chunk so that only two accumulators and the
+    // coefficients are live at once (register pressure)
+    const v8h* sV = static_cast<const v8h*>(sVraw);
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu) {
+      forward();
+      v16f oh = zf, ol = zf;
+#pragma unroll
+      for (int kappa = 0; kappa < R8; ++kappa) {
+        const int g = kappa & 3;
+        const v16i& A = acc[kappa >> 2];
+        v8h Bh, Bl;
+        split_fp16_64(A[4 * g], A[4 * g + 1], A[4 * g + 2], A[4 * g + 3], Bh, Bl);
+        const v8h Wt = sV[(mu * 8 + kappa) * 64 + lane];
+        oh = __builtin_amdgcn_mfma_f32_32x32x16_f16(Wt, Bh, oh, 0, 0, 0);
+        ol = __builtin_amdgcn_mfma_f32_32x32x16_f16(Wt, Bl, ol, 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // one pixel chunk's accumulators live at a time (register pressure)
+      __builtin_amdgcn_sched_barrier(0);
+      finish(oh + ol, mu);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   } else {
     // FP32 inverse: one coefficient per lane and instruction (K = lane / 32)
     const float* sVf = static_cast<const float*>(sVraw);
+    v16f out[2] = {zf, zf};
 #pragma unroll
     for (int kappa = 0; kappa < R8; ++kappa) {
       const int g = kappa & 3;
@@ -139,39 +235,8 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-  }
-  // Reconstruction: register 4g + v of pixel chunk mu is pixel row
-  // 4 mu + 2h + g / 2, column 4 (g % 2) + v of this lane's block.
-#pragma unroll
-  for (int mu = 0; mu < 2; ++mu) {
-    uint32_t w[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      uint32_t word = 0;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(fmaf(out[mu][4 * g + v], inv, bias), v, word);
-      w[g] = word;
-    }
-    // unconditional stores: lanes without a block carry an out-of-range
-    // offset and the buffer unit drops their writes
-#pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-      u32x2 o;
-      o.x = w[2 * rr];
-      o.y = w[2 * rr + 1];
-      __builtin_amdgcn_raw_buffer_store_b64(o, rd, od, (4 * mu + rr) * pd, 0);
-    }
-    if (valid) {
-#pragma unroll
-      for (int rr = 0; rr < 2; ++rr) {
-        sxx = __builtin_amdgcn_udot4(px[mu][rr].x, px[mu][rr].x, sxx, false);
-        sxx = __builtin_amdgcn_udot4(px[mu][rr].y, px[mu][rr].y, sxx, false);
-        sxx = __builtin_amdgcn_udot4(w[2 * rr], w[2 * rr], sxx, false);
-        sxx = __builtin_amdgcn_udot4(w[2 * rr + 1], w[2 * rr + 1], sxx, false);
-        sxy = __builtin_amdgcn_udot4(px[mu][rr].x, w[2 * rr], sxy, false);
-        sxy = __builtin_amdgcn_udot4(px[mu][rr].y, w[2 * rr + 1], sxy, false);
-      }
-    }
+    finish(out[0], 0);
+    finish(out[1], 1);
   }
 }
 
@@ -240,7 +305,7 @@ __device__ __forceinline__ void segment(const SegImage& im, int base0, int be, i
     for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
       for (int rr = 0; rr < 2; ++rr)
-        px[cc][rr] = __builtin_amdgcn_raw_buffer_load_b64(im.rs, off, (4 * cc + rr) * ps, 0);
+        px[cc][rr] = __builtin_amdgcn_raw_buffer_load_b64(im.rs, off, (4 * cc + rr) * ps, RKLT_MFMA_LOAD_AUX);
   };
   Cursor cl{0, 0};
   if (WIDE) {
@@ -271,15 +336,24 @@ __device__ __forceinline__ void segment(const SegImage& im, int base0, int be, i
     load(px, cl, base + RKLT_MFMA_RING * stride);
     advance(cl);
   };
-  for (int base = base0; base < be; base += RKLT_MFMA_RING * stride) {
+  // Whole rounds of the ring, then the remaining steps.  No step exits the
+  // loop early, so the memory operations between a load and its use are the
+  // same on every path and the load's wait leaves the later loads in flight.
+  const int nsteps = base0 < be ? (be - base0 + stride - 1) / stride : 0;
+  int base = base0;
+  for (int g = nsteps / RKLT_MFMA_RING; g > 0; --g) {
     run(p0, base);
-    if (base + stride >= be) break;
     run(p1, base + stride);
 #if RKLT_MFMA_RING == 3
-    if (base + 2 * stride >= be) break;
     run(p2, base + 2 * stride);
 #endif
+    base += RKLT_MFMA_RING * stride;
   }
+  const int rem = nsteps % RKLT_MFMA_RING;
+  if (rem > 0) run(p0, base);
+#if RKLT_MFMA_RING == 3
+  if (rem > 1) run(p1, base + stride);
+#endif
 }
 
 template <int R8, int PATH>
@@ -325,12 +399,15 @@ void rklt_mfma8_kernel(KArgs a) {
     const int tid = __builtin_amdgcn_readfirstlane(im->tid);
     const int r = __builtin_amdgcn_readfirstlane(im->r);
     const DevTransform* tf = a.tf + tid;
-    if (tid != loaded || r != loaded_r) {
+    const int path = __builtin_amdgcn_readfirstlane(mfma8_path(*tf, r));
+    // the inverse operand in LDS: fp16 (forms 1 and 3) or FP32 (form 2)
+    const int operand = 2 * tid + (path == 2);
+    if (operand != loaded || r != loaded_r) {
       __syncthreads();
-      if (tid != loaded) {
-        // the inverse operand of the transform's path (fp16 split or FP32), 16 KB either way
-        const uint4* srcv = tf->mfma == 1 ? reinterpret_cast<const uint4*>(&tf->mV[0][0][0][0])
-                                          : reinterpret_cast<const uint4*>(&tf->mVf[0][0][0][0]);
+      if (operand != loaded) {
+        // 16 KB either way
+        const uint4* srcv = path != 2 ? reinterpret_cast<const uint4*>(&tf->mV[0][0][0][0])
+                                      : reinterpret_cast<const uint4*>(&tf->mVf[0][0][0][0]);
         for (int k = threadIdx.x; k < 2 * 8 * 64; k += blockDim.x) sV[k] = srcv[k];
       }
       // forward operand: rows (zig-zag ranks) >= r zeroed
@@ -341,11 +418,11 @@ void rklt_mfma8_kernel(KArgs a) {
         sF[k] = keep ? v4i{f.x, f.y, f.z, f.w} : v4i{0, 0, 0, 0};
       }
       __syncthreads();
-      loaded = tid;
+      loaded = operand;
       loaded_r = r;
     }
     const int R8 = (r + 7) >> 3;
-    const float inv = tf->inv_den2, bias = tf->bias;
+    const float inv = tf->m_inv, bias = tf->m_bias;
     const int tb = im->tile_blocks, nblocks = im->nblocks;
     const int bs = (t - tile0) * tb;
     const int be = (seg_end - tile0) * tb < nblocks ? (seg_end - tile0) * tb : nblocks;
@@ -363,16 +440,17 @@ void rklt_mfma8_kernel(KArgs a) {
     }
     uint32_t sxx = 0, sxy = 0;
     const int base0 = bs + wave * 32;
-    const int path = __builtin_amdgcn_readfirstlane(tf->mfma);
 #define RKLT_SEG(RR)                                                                                   \
   case RR:                                                                                             \
     if (path == 1) segment_any<RR, 1>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); \
+    else if (path == 3) segment_any<RR, 3>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy); \
     else segment_any<RR, 2>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);           \
     break;
     switch (R8) {
       RKLT_SEG(1) RKLT_SEG(2) RKLT_SEG(3) RKLT_SEG(4) RKLT_SEG(5) RKLT_SEG(6) RKLT_SEG(7)
       default:
         if (path == 1) segment_any<8, 1>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
+        else if (path == 3) segment_any<8, 3>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
         else segment_any<8, 2>(si, base0, be, stride, sF, sV, lane, q, h, inv, bias, sxx, sxy);
         break;
     }

@@ -40,8 +40,14 @@ struct alignas(256) DevTransform {
   float inv_den2, bias;
   int32_t adj[64];
   float fadj[64];                // m*8 + i
-  // N = 8 matrix-core operands, in the lane layout of the instructions
-  // (mfma = 1 when the exact inverse also fits fp16 operands; see abi.cpp):
+  // N = 8 matrix-core kernel (m_ok = 1 when its operands are built).  The
+  // inverse of an image with r kept coefficients takes form
+  //   1 when r <= m_r1: exact, one fp16 pass (mV);
+  //   3 otherwise when m_path3: exact, fp16 with two accumulators (mV);
+  //   2 otherwise: FP32 (mVf);
+  // and the pixel is RNE_sat(Out * m_inv + m_bias) (exact forms: 1/den^2 and
+  // 128 + delta; FP32 form without an exact inverse: 1 and 128 + 2^-12).
+  // Operands, in the lane layout of the instructions:
   //   mF[mu][c][lane][w]   forward A operand of v_mfma_i32_32x32x32_i8, int8x4
   //                        words: row = zig-zag rank 32 mu + lane % 32, K =
   //                        pixel of K-chunk c; value T[i][m] T[j][n]
@@ -50,12 +56,13 @@ struct alignas(256) DevTransform {
   //                        coefficient chunk kappa, halves ordered hi v0, hi v1,
   //                        lo v0, lo v1, hi v2, hi v3, lo v2, lo v3 for the
   //                        ranks 8 kappa + 4 (lane / 32) + v; value adj[m][i] adj[n][j]
-  //   mVf[mu][kappa][v][lane] inverse A operand of v_mfma_f32_32x32x2_f32 for
-  //                        transforms without a small exact inverse (exact =
-  //                        0): row = pixel, K = lane / 32 selects rank
-  //                        8 kappa + 4 (lane / 32) + v; value (T^-1 (x) T^-1) in FP32
-  int32_t mfma;
-  int32_t pad_mfma[3];
+  //   mVf[mu][kappa][v][lane] inverse A operand of v_mfma_f32_32x32x2_f32:
+  //                        row = pixel, K = lane / 32 selects rank
+  //                        8 kappa + 4 (lane / 32) + v; value adj (x) adj with
+  //                        an exact inverse, else T^-1 (x) T^-1, in FP32
+  int32_t m_ok, m_r1, m_path3, m_den;
+  float m_inv, m_bias;
+  int32_t m_pad[2];
   int32_t mF[2][2][64][4];
   _Float16 mV[2][8][64][8];
   float mVf[2][8][4][64];
@@ -94,6 +101,12 @@ struct KArgs {
 
 // Number of anti-diagonals i + j < D that contain the first r zig-zag
 // positions of an N x N block.
+// Inverse form of the matrix-core kernel for r kept coefficients (see
+// DevTransform): 1 and 3 exact, 2 FP32.
+__host__ __device__ inline int mfma8_path(const DevTransform& t, int r) {
+  return r <= t.m_r1 ? 1 : t.m_path3 ? 3 : 2;
+}
+
 inline int diagonals_for(int N, int r) {
   int D = 0, covered = 0;
   while (covered < r) {

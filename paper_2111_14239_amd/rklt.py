@@ -93,6 +93,7 @@ def _load():
         "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 3)]),
         "rklt_plan_update": (st, [vp, C.POINTER(Image), C.c_int32, vp]),
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+        "rklt_ctx_mfma_form": (st, [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -105,7 +106,7 @@ _lib = _load()
 EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_create",
             "rklt_ctx_destroy", "rklt_ctx_add_transform", "rklt_codec", "rklt_plan_create",
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
-            "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update")
+            "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form")
 
 
 def lib():
@@ -257,6 +258,13 @@ class Context:
         e, d = C.c_int32(), C.c_int64()
         _check(_lib.rklt_ctx_transform_exact(self._h, int(tid), C.byref(e), C.byref(d)))
         return bool(e.value), int(d.value)
+
+    def mfma_form(self, tid: int, r: int) -> int:
+        """Inverse form of the N = 8 matrix-core kernel for (transform, r):
+        1 or 3 exact, 2 FP32, 0 not on that kernel."""
+        f = C.c_int32()
+        _check(_lib.rklt_ctx_mfma_form(self._h, int(tid), int(r), C.byref(f)))
+        return int(f.value)
 
     def codec(self, img: Image, res_ptr: int, tuning: Tuning | None = None, stream=None):
         """rklt_codec: one image, one launch (plain path)."""

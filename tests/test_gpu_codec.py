@@ -48,7 +48,9 @@ def run_plain(ctx, img, N, rho, alpha, r, ell=128, dump=True, recon=True):
                                               with_recon=recon, dump=dump)
     torch.cuda.synchronize()
     out = rklt.read_results(res)[0]
-    out["exact"] = is_exact(ctx, N, rho, alpha, ell)
+    # with a dump the register kernel codes the image, without one the
+    # matrix-core kernel; each reports its own exactness
+    out["exact"] = is_exact(ctx, N, rho, alpha, ell) if dump else mc_exact(ctx, N, rho, alpha, r, ell)
     out["recon"] = dst.cpu().numpy() if dst is not None else None
     out["coef"] = coef.cpu().numpy() if coef is not None else None
     out["scaled"] = scaled.cpu().numpy() if scaled is not None else None
@@ -59,6 +61,12 @@ def is_exact(ctx, N, rho, alpha, ell):
     """The N = 8 register kernel (level shift 128) reconstructs exactly when
     the library found a small exact inverse of T."""
     return N == 8 and ell == 128 and ctx.transform_exact(ctx.transform_id(N, rho, alpha))[0]
+
+
+def mc_exact(ctx, N, rho, alpha, r, ell):
+    """The N = 8 matrix-core kernel (level shift 128) reconstructs exactly in
+    its inverse forms 1 and 3."""
+    return N == 8 and ell == 128 and ctx.mfma_form(ctx.transform_id(N, rho, alpha), r) in (1, 3)
 
 
 def check_against_oracle(img, N, rho, alpha, r, ell, got, check_coef=True):
@@ -225,7 +233,7 @@ def test_batched_plan_matches_alone_and_oracle(ctx, tuning):
         assert g["sse"] == alone["sse"] and g["psnr_db"] == alone["psnr_db"], spec
         g["recon"] = d.cpu().numpy()
         g["coef"] = None
-        g["exact"] = is_exact(ctx, 8, rho, alpha, ell)
+        g["exact"] = mc_exact(ctx, 8, rho, alpha, r, ell)
         check_against_oracle(img, 8, rho, alpha, r, ell, g, check_coef=False)
     # the results array is reusable without clearing, and runs are deterministic
     plan.run(int(res.data_ptr()))
@@ -323,12 +331,28 @@ def test_exact_inverse_coverage(ctx):
     inexact = sorted(k for k, (ex, _) in dens.items() if not ex)
     assert inexact and all(k[0] == 3.0 and 0.05 <= k[1] <= 0.13 for k in inexact), inexact
     assert dens[(2.0, 0.95)] == (True, 24) and dens[(2.0, 0.2)] == (True, 6)
-    # the FP32 fallback still meets the 1-LSB / tie bar
+    # the register kernel's FP32 fallback still meets the 1-LSB / tie bar
     img = ar1_image(136, 264, 0.1, seed=5)
     for r in (1, 10, 64):
         got = run_plain(ctx, img, 8, 0.1, 3.0, r)
         assert not got["exact"]
         check_against_oracle(img, 8, 0.1, 3.0, r, 128, got)
+    # the matrix-core kernel is exact for every one of these transforms and
+    # every r: one fp16 pass while its partial sums stay below 2^24, two
+    # accumulators beyond (the den-60 transform at large r)
+    forms = {}
+    for alpha in (2.0, 3.0):
+        for rho in np.linspace(0.01, 0.99, 99):
+            tid = ctx.transform_id(8, float(rho), alpha)
+            forms[(alpha, round(float(rho), 2))] = [ctx.mfma_form(tid, r) for r in range(1, 65)]
+    assert all(f in (1, 3) for fs in forms.values() for f in fs)
+    den60 = forms[(3.0, 0.1)]
+    assert den60[0] == 1 and den60[-1] == 3 and 3 in den60 and sorted(den60) == den60
+    assert all(f == 1 for k, fs in forms.items() if k not in inexact for f in fs)
+    for r in (1, 40, 44, 45, 46, 47, 50, 57, 64):
+        got = run_plain(ctx, img, 8, 0.1, 3.0, r, dump=False)
+        assert got["exact"], r
+        check_against_oracle(img, 8, 0.1, 3.0, r, 128, got, check_coef=False)
 
 
 def test_plan_kernel_classes(ctx):
@@ -343,7 +367,8 @@ def test_plan_kernel_classes(ctx):
     torch.cuda.synchronize()
     for (img, x), d, g, spec in zip(xs, dsts, rklt.read_results(res), specs):
         H, W, rho, alpha, r, seed, ell = spec
-        g.update(recon=d.cpu().numpy(), coef=None, exact=is_exact(ctx, 8, rho, alpha, ell))
+        g.update(recon=d.cpu().numpy(), coef=None, exact=mc_exact(ctx, 8, rho, alpha, r, ell))
+        assert g["exact"], spec
         check_against_oracle(img, 8, rho, alpha, r, ell, g, check_coef=False)
     plan.close()
 
