@@ -137,6 +137,128 @@ def serving(ctx, seconds: float, streams: int) -> dict:
             "rates": out}
 
 
+UNEVEN_IMAGES = 2000
+WORKERS = min(16, os.cpu_count() or 1)
+
+
+def _time_plan(plan, res, stream, steps: int) -> float:
+    """Milliseconds per launch over `steps` back-to-back launches."""
+    import torch
+    for _ in range(3):
+        plan.run(int(res.data_ptr()), stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(steps):
+        plan.run(int(res.data_ptr()), stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def uneven(ctx, steps: int) -> dict:
+    """The uneven batch: 2000 AR(1) images of mixed sizes in one persistent
+    launch, with the library's default tiling and after its autotuner."""
+    import torch
+
+    from paper_2111_14239_amd import rklt
+    from paper_2111_14239_amd.inputs import uneven_batch
+
+    specs = uneven_batch(UNEVEN_IMAGES)
+    with ProcessPoolExecutor(max_workers=WORKERS) as ex:
+        srcs = [torch.from_numpy(a).to("cuda") for a in ex.map(_gen, specs, chunksize=8)]
+    dsts = [torch.empty_like(x) for x in srcs]
+    descs = [rklt.image_desc(x, ctx.transform_id(8, s.rho, s.alpha), s.r, dst=d)
+             for x, d, s in zip(srcs, dsts, specs)]
+    pixels = sum(s.H * s.W for s in specs)
+    res = rklt.new_results(len(specs))
+    stream = torch.cuda.current_stream()
+    plan = ctx.plan(descs)
+    ms_default = _time_plan(plan, res, stream, steps)
+    tiles_default = plan.tiles
+    t = plan.autotune(int(res.data_ptr()), reps=5, stream=stream)
+    ms_tuned = _time_plan(plan, res, stream, steps)
+    out = {"images": len(specs), "pixels": pixels,
+           "ms_per_launch_default": ms_default, "tiles_default": tiles_default,
+           "ms_per_launch_autotuned": ms_tuned, "tiles_autotuned": plan.tiles,
+           "autotuned": {"wg_threads": t.wg_threads, "blocks_per_thread": t.blocks_per_thread},
+           "value": pixels / (ms_tuned / 1e3) / 1e6, "unit": "Mpixel/s",
+           "hbm_frac": BYTES_PER_PIXEL * pixels / (ms_tuned / 1e3) / 1e9 / HBM_PEAK_GBS,
+           "launches": plan.launches, "grid_wgs": plan.grid}
+    plan.close()
+    return out
+
+
+def single(ctx, steps: int) -> dict:
+    """One 512 x 512 image (rho = 0.95, alpha = 2, r = 10) on the plain path:
+    launch-bound, so reported as latency."""
+    import torch
+
+    from paper_2111_14239_amd import rklt
+    from paper_2111_14239_amd.inputs import single_image
+
+    s = single_image()
+    x = torch.from_numpy(s.image()).to("cuda")
+    d = torch.empty_like(x)
+    res = rklt.new_results(1)
+    desc = rklt.image_desc(x, ctx.transform_id(s.N, s.rho, s.alpha), s.r, dst=d, level_shift=s.ell)
+    stream = torch.cuda.current_stream()
+    for _ in range(10):
+        ctx.codec(desc, int(res.data_ptr()), None, stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        ctx.codec(desc, int(res.data_ptr()), None, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(steps):
+        ctx.codec(desc, int(res.data_ptr()), None, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    r = rklt.read_results(res)[0]
+    return {"workload": "512x512 AR(1), rho 0.95, alpha 2, r 10, plain path",
+            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+            "ms_per_image_back_to_back": a.elapsed_time(b) / steps, "psnr_db": r["psnr_db"]}
+
+
+def block_sizes(ctx, steps: int) -> dict:
+    """64 AR(1) images of 2048 x 2048 (rho = 0.9) for N in {4, 16, 32},
+    alpha = 8 / max|K| (largest entry of T is 8), r keeping 10/64 of the
+    coefficients and r = N^2; one plan per (N, r)."""
+    import torch
+
+    from paper_2111_14239_amd import rklt
+    from paper_2111_14239_amd.inputs import large_block_batch
+
+    out = {}
+    for N in (4, 16, 32):
+        specs = large_block_batch(N)
+        gamma = float(np.max(np.abs(rklt.build_transform(N, 0.9, 64.0).K)))  # K does not depend on alpha
+        alpha = 8.0 / gamma
+        tid = ctx.transform_id(N, 0.9, alpha)
+        with ProcessPoolExecutor(max_workers=WORKERS) as ex:
+            srcs = [torch.from_numpy(a).to("cuda") for a in ex.map(_gen, specs, chunksize=2)]
+        dsts = [torch.empty_like(x) for x in srcs]
+        pixels = sum(s.H * s.W for s in specs)
+        res = rklt.new_results(len(specs))
+        stream = torch.cuda.current_stream()
+        for r in sorted({specs[0].r, N * N}):
+            plan = ctx.plan([rklt.image_desc(x, tid, r, dst=d) for x, d in zip(srcs, dsts)])
+            ms = _time_plan(plan, res, stream, steps)
+            out[f"N{N}_r{r}"] = {"ms_per_launch": ms, "value": pixels / (ms / 1e3) / 1e6, "unit": "Mpixel/s",
+                                 "hbm_frac": BYTES_PER_PIXEL * pixels / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                 "alpha": alpha, "launches": plan.launches}
+            plan.close()
+        del srcs, dsts
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +273,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="seconds of Poisson arrivals per serving rate (0 skips serving)")
     ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--no-uneven", action="store_true", help="skip the 2000-image uneven batch")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-image latency and the N in {4, 16, 32} batches")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -172,7 +297,7 @@ def main():
             if e.status != rklt.E_SINGULAR:
                 raise
             rejected += 1
-    with ProcessPoolExecutor(max_workers=8) as ex:
+    with ProcessPoolExecutor(max_workers=WORKERS) as ex:
         imgs = list(ex.map(_gen, specs, chunksize=4))
     n = len(specs)
     H = W = 1024
@@ -288,6 +413,11 @@ def main():
     }
     plan.close()
     del src, dst
+    if not args.no_extra:
+        line["single_image"] = single(ctx, 200)
+        line["block_sizes"] = block_sizes(ctx, max(5, args.steps // 20))
+    if not args.no_uneven:
+        line["uneven_batch"] = uneven(ctx, max(10, args.steps // 4))
     if args.serve_seconds > 0:
         line["serving"] = serving(ctx, args.serve_seconds, args.serve_streams)
     if not args.no_cpu_baseline:

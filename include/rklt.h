@@ -193,6 +193,19 @@ rklt_status rklt_plan_create(rklt_ctx* ctx, const rklt_image* imgs, int32_t n,
                              const rklt_tuning* tuning, rklt_plan** out);
 /* d_res: n device rklt_result, in the order of the plan's images. */
 rklt_status rklt_plan_run(rklt_plan* plan, rklt_result* d_res, void* stream);
+/* Tile-shape autotuning of the batched launch (a persistent grid over
+ * uneven images; the tile shape and blocks per workgroup decide balance and
+ * per-tile overhead): re-tiles the plan for each candidate tuning
+ * (wg_threads in {128, 256} x blocks_per_thread in {1, 2, 4, 8}, grid at the
+ * resident capacity), times `reps` runs of each on `stream` with HIP events
+ * after one warm-up run, and keeps the fastest.  The runs code the plan's
+ * images for real: dst and d_res hold a complete, valid result afterwards.
+ * Synchronous (waits for the timing runs).  `chosen` (may be NULL) receives
+ * the tuning kept.  Errors: E_INVAL (NULL plan or d_res, reps outside
+ * 1..1000), E_STATE (empty plan), E_HIP; after an error the plan keeps its
+ * previous tuning (or holds no images if re-tiling failed). */
+rklt_status rklt_plan_autotune(rklt_plan* plan, rklt_result* d_res, int32_t reps, void* stream,
+                               rklt_tuning* chosen);
 /* Replace the plan's images with `n` new ones (same rules as
  * rklt_plan_create; the tuning given at creation is kept) without a
  * synchronous copy: the work list is rebuilt on the host and uploaded with an

@@ -52,6 +52,8 @@ struct rklt_plan {
   std::vector<unsigned char> h_image;
   void* h_pinned = nullptr;
   size_t h_cap = 0;
+  // the caller's descriptors of the current images (for re-tiling)
+  std::vector<rklt_image> images;
 };
 
 namespace rklt {
@@ -538,13 +540,17 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
 
 namespace {
 
-// Relative cost of one N x N block in the matrix-core kernel, measured on
-// MI355X for each inverse form and number R8 = ceil(r / 8) of 8-coefficient
-// chunks: a fixed part per step plus a part per chunk (the FP32 form runs
-// eight 32x32x2 products per chunk).
+// Cost of one 8x8 block in the matrix-core kernel for each inverse form and
+// number R8 = ceil(r / 8) of 8-coefficient chunks: picoseconds per block of
+// a full-chip launch, measured on MI355X with batches of one form and one R8.
+// Form 1 is bound by memory up to 32 coefficients; forms 3 and 2 (two
+// accumulators; eight 32x32x2 products per chunk) by the matrix cores.
 double mfma8_block_cost(int path, int r) {
+  static const double form1[8] = {22.3, 21.9, 22.1, 22.2, 22.9, 24.4, 26.2, 26.9};
   const int R8 = (r + 7) / 8;
-  return path == 1 ? 0.0760 + 0.0030 * R8 : path == 3 ? 0.0760 + 0.0080 * R8 : 0.0626 + 0.0182 * R8;
+  if (path == 1) return form1[R8 - 1];
+  if (path == 3) return 21.0 + 3.3 * R8;
+  return 17.6 + 5.1 * R8;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
@@ -650,6 +656,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
     for (int k = 0; k < n; ++k)
       by_class[kernel_class(ctx->host[imgs[k].transform_id], imgs[k].level_shift, dump)].push_back(all[k]);
   }
+  p->images.assign(imgs, imgs + n);
   p->N = N;
   p->dump = dump;
   p->n = n;
@@ -758,6 +765,85 @@ rklt_status rklt_plan_update(rklt_plan* p, const rklt_image* imgs, int32_t n, vo
     p->nparts = 0;
     return hip_fail("rklt_plan_update: hipMemcpyAsync", e);
   }
+  return RKLT_OK;
+}
+
+rklt_status rklt_plan_autotune(rklt_plan* p, rklt_result* d_res, int32_t reps, void* stream, rklt_tuning* chosen) {
+  clear_error();
+  if (!p || !d_res) return fail(RKLT_E_INVAL, "rklt_plan_autotune: NULL argument");
+  if (reps < 1 || reps > 1000) return fail(RKLT_E_INVAL, "rklt_plan_autotune: reps=%d outside 1..1000", reps);
+  if (p->nparts == 0) return fail(RKLT_E_STATE, "rklt_plan_autotune: the plan holds no images");
+  hipError_t e = use_device(p->ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const rklt_tuning orig = p->tuning;
+  const bool orig_has = p->has_tuning;
+  const std::vector<rklt_image> imgs = p->images;
+  // re-tile the plan with tuning `t` and upload its work list
+  auto apply = [&](const rklt_tuning& t, bool has) -> rklt_status {
+    p->tuning = t;
+    p->has_tuning = has;
+    rklt_status s = build_plan(p, imgs.data(), static_cast<int32_t>(imgs.size()));
+    if (!s) s = ensure_device_capacity(p);
+    if (!s) {
+      const hipError_t he = hipMemcpyAsync(p->d_buf, p->h_image.data(), p->h_image.size(), hipMemcpyHostToDevice, st);
+      if (he == hipSuccess) {
+        const hipError_t hs = hipStreamSynchronize(st);
+        if (hs != hipSuccess) s = hip_fail("rklt_plan_autotune: hipStreamSynchronize", hs);
+      } else {
+        s = hip_fail("rklt_plan_autotune: hipMemcpyAsync", he);
+      }
+    }
+    if (s) p->nparts = 0;
+    return s;
+  };
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if ((e = hipEventCreate(&ev[0])) != hipSuccess || (e = hipEventCreate(&ev[1])) != hipSuccess) {
+    if (ev[0]) (void)hipEventDestroy(ev[0]);
+    return hip_fail("rklt_plan_autotune: hipEventCreate", e);
+  }
+  // candidates: workgroup size and blocks per thread (tile size); the grid
+  // stays at the resident capacity
+  static const int kWg[] = {128, 256};
+  static const int kBpt[] = {1, 2, 4, 8};
+  rklt_tuning best{};
+  float best_ms = -1.0f;
+  rklt_status st_out = RKLT_OK;
+  for (int wg : kWg) {
+    for (int bpt : kBpt) {
+      const rklt_tuning t{wg, bpt, 0, 0};
+      if ((st_out = apply(t, true))) break;
+      if ((st_out = rklt_plan_run(p, d_res, stream))) break;  // warm-up
+      (void)hipEventRecord(ev[0], st);
+      for (int k = 0; k < reps && !st_out; ++k) st_out = rklt_plan_run(p, d_res, stream);
+      (void)hipEventRecord(ev[1], st);
+      if (st_out) break;
+      if ((e = hipEventSynchronize(ev[1])) != hipSuccess) {
+        st_out = hip_fail("rklt_plan_autotune: hipEventSynchronize", e);
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (best_ms < 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+    if (st_out) break;
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st_out) {
+    // keep the error message of the failure; restore the original tiling
+    char msg[sizeof(g_error)];
+    std::memcpy(msg, g_error, sizeof(msg));
+    (void)apply(orig, orig_has);
+    std::memcpy(g_error, msg, sizeof(msg));
+    return st_out;
+  }
+  rklt_status s = apply(best, true);
+  if (s) return s;
+  if (chosen) *chosen = best;
   return RKLT_OK;
 }
 

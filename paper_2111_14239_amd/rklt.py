@@ -94,6 +94,7 @@ def _load():
         "rklt_plan_update": (st, [vp, C.POINTER(Image), C.c_int32, vp]),
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_ctx_mfma_form": (st, [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+        "rklt_plan_autotune": (st, [vp, vp, C.c_int32, vp, C.POINTER(Tuning)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -106,7 +107,8 @@ _lib = _load()
 EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_create",
             "rklt_ctx_destroy", "rklt_ctx_add_transform", "rklt_codec", "rklt_plan_create",
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
-            "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form")
+            "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form",
+            "rklt_plan_autotune")
 
 
 def lib():
@@ -308,6 +310,15 @@ class Plan:
         arr = (Image * len(imgs))(*imgs)
         _check(_lib.rklt_plan_update(self._h, arr, len(imgs), C.c_void_p(_stream_handle(stream))))
         self._refresh(len(imgs))
+
+    def autotune(self, res_ptr: int, reps: int = 10, stream=None) -> Tuning:
+        """rklt_plan_autotune: time the candidate tile shapes on this plan's
+        images and keep the fastest; returns the tuning kept."""
+        t = Tuning()
+        _check(_lib.rklt_plan_autotune(self._h, C.c_void_p(res_ptr), int(reps),
+                                       C.c_void_p(_stream_handle(stream)), C.byref(t)))
+        self._refresh(self.n)
+        return t
 
     def close(self):
         if self._h:

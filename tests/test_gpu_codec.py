@@ -424,3 +424,71 @@ def test_largest_image_grows_tiles(ctx):
     assert np.max(np.abs(diff)) <= 1
     frac = ref["pre_round"] - np.floor(ref["pre_round"])
     assert np.all((np.abs(frac - 0.5) <= TIE_BAND[N])[diff != 0])
+
+
+def test_uneven_batch_full_size(ctx):
+    # the 2000-image uneven batch at full size (about 1.86 Gpixel, random
+    # pixels: the kernels' work does not depend on the values), in the launch
+    # configuration the benchmark times and after the autotuner: every image
+    # equals the plain path bit for bit, and sampled blocks match the oracle
+    from paper_2111_14239_amd.inputs import uneven_batch
+    specs = uneven_batch(2000)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3000)
+    srcs = [torch.randint(0, 256, (s.H, s.W), dtype=torch.uint8, device="cuda", generator=g) for s in specs]
+    dsts = [torch.empty_like(x) for x in srcs]
+    tids = [ctx.transform_id(8, s.rho, s.alpha) for s in specs]
+    descs = [rklt.image_desc(x, t, s.r, dst=d) for x, d, t, s in zip(srcs, dsts, tids, specs)]
+    assert sum(s.H * s.W for s in specs) > 1.5e9
+    plan = ctx.plan(descs)
+    assert plan.launches == 1
+    res = rklt.new_results(len(specs))
+    plan.run(int(res.data_ptr()))
+    res_plain = rklt.new_results(len(specs))
+    ref = torch.empty(max(x.numel() for x in srcs), dtype=torch.uint8, device="cuda")
+    got = rklt.read_results(res)
+    for k, (x, d, s) in enumerate(zip(srcs, dsts, specs)):
+        r2 = ref[:x.numel()].view(s.H, s.W)
+        ctx.codec(rklt.image_desc(x, tids[k], s.r, dst=r2), int(res_plain.data_ptr()) + k * rklt.RESULT_BYTES)
+        assert torch.equal(d, r2), k
+    plain = rklt.read_results(res_plain)
+    assert [p["sse"] for p in plain] == [q["sse"] for q in got]
+    # autotuned tiling: same results
+    t = plan.autotune(int(res.data_ptr()), reps=1)
+    assert t.wg_threads in (128, 256) and t.blocks_per_thread in (1, 2, 4, 8)
+    torch.cuda.synchronize()
+    assert [q["sse"] for q in rklt.read_results(res)] == [p["sse"] for p in plain]
+    # sampled blocks of a few images against the oracle
+    rng = np.random.default_rng(7)
+    for k in rng.choice(len(specs), size=4, replace=False):
+        s = specs[k]
+        img = srcs[k].cpu().numpy()
+        rec = dsts[k].cpu().numpy()
+        picks = rng.integers(0, [s.H // 8, s.W // 8], size=(64, 2))
+        strip_in = np.concatenate([img[8 * a:8 * a + 8, 8 * b:8 * b + 8] for a, b in picks], axis=1)
+        strip_out = np.concatenate([rec[8 * a:8 * a + 8, 8 * b:8 * b + 8] for a, b in picks], axis=1)
+        ref_o = o.codec(strip_in, 8, s.rho, s.alpha, s.r, 128)
+        assert mc_exact(ctx, 8, s.rho, s.alpha, s.r, 128)
+        assert np.array_equal(strip_out, ref_o["recon"]), k
+    plan.close()
+
+
+def test_autotune_keeps_results_and_rejects_bad_arguments(ctx):
+    xs, dsts, plan, res = _batch(ctx, UNEVEN)
+    plan.run(int(res.data_ptr()))
+    torch.cuda.synchronize()
+    before = [(q["sse"], q["psnr_db"]) for q in rklt.read_results(res)]
+    recon = [d.cpu().numpy() for d in dsts]
+    t = plan.autotune(int(res.data_ptr()), reps=2)
+    torch.cuda.synchronize()
+    assert [(q["sse"], q["psnr_db"]) for q in rklt.read_results(res)] == before
+    assert all(np.array_equal(d.cpu().numpy(), r) for d, r in zip(dsts, recon))
+    assert (t.wg_threads, t.blocks_per_thread) in {(w, b) for w in (128, 256) for b in (1, 2, 4, 8)}
+    with pytest.raises(rklt.RkltError) as e:
+        plan.autotune(int(res.data_ptr()), reps=0)
+    assert e.value.status == rklt.E_INVAL
+    # the plan still runs after the rejected call
+    plan.run(int(res.data_ptr()))
+    torch.cuda.synchronize()
+    assert [(q["sse"], q["psnr_db"]) for q in rklt.read_results(res)] == before
+    plan.close()
