@@ -142,6 +142,7 @@ rklt_status check_image(rklt_ctx* ctx, const rklt_image& im, int index, DevImage
   d.ell = im.level_shift;
   d.D = diagonals_for(N, im.r);
   d.bw = im.W / N;
+  d.bwp = d.bw;
   d.nblocks = (im.H / N) * (im.W / N);
   *N_out = N;
   return RKLT_OK;
@@ -520,6 +521,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     if ((st = check_image(ctx, *img, 0, &a.one, &N))) return st;
     a.dump = (img->coef_out || img->scaled_out) ? 1 : 0;
     const int cls = kernel_class(ctx->host[img->transform_id], img->level_shift, a.dump != 0);
+    if (cls == 2) mfma8_pad_rows(a.one);
     a.one.tile0 = 0;
     a.one.slot = 0;
     a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
@@ -653,8 +655,11 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
       all.push_back(d);
     }
     // a plan that dumps coefficients keeps every image on a dumping kernel
-    for (int k = 0; k < n; ++k)
-      by_class[kernel_class(ctx->host[imgs[k].transform_id], imgs[k].level_shift, dump)].push_back(all[k]);
+    for (int k = 0; k < n; ++k) {
+      const int cls = kernel_class(ctx->host[imgs[k].transform_id], imgs[k].level_shift, dump);
+      if (cls == 2) mfma8_pad_rows(all[k]);
+      by_class[cls].push_back(all[k]);
+    }
   }
   p->images.assign(imgs, imgs + n);
   p->N = N;

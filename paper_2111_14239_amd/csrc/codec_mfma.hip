@@ -249,10 +249,11 @@ __device__ __forceinline__ void mfma_step(const u32x2 (&px)[2][2], const v4i* sF
 constexpr uint32_t kOutOfRange = 0x80000000u;
 constexpr int kRawBufferFlags = 0x00020000;
 
-// Wave-uniform fields of the image a segment codes (held in SGPRs).
+// Wave-uniform fields of the image a segment codes (held in SGPRs): bw
+// blocks per row, bwp blocks per row of the block index space.
 struct SegImage {
   __amdgpu_buffer_rsrc_t rs, rd;
-  int ps, pd, bw;
+  int ps, pd, bw, bwp;
 };
 
 // Block row and column of the first block of a wave's step, wave-uniform:
@@ -265,42 +266,47 @@ struct Cursor {
 // Steps [base0, be) of one image segment, 32 blocks per step, strided by
 // the workgroup's waves.  A ring of RKLT_MFMA_RING pixel buffers keeps the
 // loads of the next steps in flight while a step is computed.  WIDE images
-// (at least 32 blocks per row) find each lane's block from a wave-uniform
-// cursor: the 32 blocks of a step wrap to the next block row at most once,
-// so a lane's offset is the cursor's offset plus one of two lane offsets.
-// Narrower images divide per lane.
+// (at least 32 blocks per row) have block rows padded to bwp, a multiple of
+// 32, and steps start at multiples of 32, so a step's 32 blocks lie in one
+// block row: a wave-uniform cursor (block row, first column) gives every
+// lane's offset as the cursor's plus a lane constant, and lanes in the
+// padding are out of range.  Narrower images divide per lane.
 template <int R8, int PATH, bool WIDE>
 __device__ __forceinline__ void segment(const SegImage& im, int base0, int be, int stride, const v4i* sF,
                                         const void* sV, int lane, int q, int h, float inv, float bias,
                                         uint32_t& sxx, uint32_t& sxy) {
-  const int bw = im.bw, ps = im.ps, pd = im.pd;
+  const int bw = im.bw, bwp = im.bwp, ps = im.ps, pd = im.pd;
   const uint32_t Ls = 8u * q + 2u * h * ps, Ld = 8u * q + 2u * h * pd;
-  const uint32_t Ws = 8u * (ps - bw), Wd = 8u * (pd - bw);
-  // byte offset of this lane's block of step `base` (cursor c) from the image
-  // start, rows 2h and up; out of range for lanes past the segment end
-  auto offset = [&](const Cursor& c, int base, int pitch, uint32_t L, uint32_t Wr) -> uint32_t {
+  // lanes of step `base` (cursor c) that hold a block of the segment
+  auto lanes = [&](const Cursor& c, int base) {
+    const int n = be - base;
+    return WIDE ? (n < bw - c.bx ? n : bw - c.bx) : n;
+  };
+  // byte offset of this lane's block of step `base` from the image start,
+  // rows 2h and up; out of range for lanes without a block
+  auto offset = [&](const Cursor& c, int base, int pitch, uint32_t L) -> uint32_t {
     uint32_t off;
     if (WIDE) {
-      off = static_cast<uint32_t>(c.by * 8 * pitch + c.bx * 8) + L + (q >= bw - c.bx ? Wr : 0u);
+      off = static_cast<uint32_t>(c.by * 8 * pitch + c.bx * 8) + L;
     } else {
       const int b = base + q;
       const int by = b / bw, bx = b - by * bw;
       off = static_cast<uint32_t>(by * 8 + 2 * h) * pitch + static_cast<uint32_t>(bx) * 8;
     }
-    return q < be - base ? off : kOutOfRange;
+    return q < lanes(c, base) ? off : kOutOfRange;
   };
   auto advance = [&](Cursor& c) {
     if (WIDE) {
       c.bx += stride;
-      while (c.bx >= bw) {
-        c.bx -= bw;
+      while (c.bx >= bwp) {
+        c.bx -= bwp;
         ++c.by;
       }
     }
   };
   // pixel rows 4c + 2h + rr of this lane's block of step `base`
   auto load = [&](u32x2 (&px)[2][2], const Cursor& c, int base) {
-    const uint32_t off = offset(c, base, ps, Ls, Ws);
+    const uint32_t off = offset(c, base, ps, Ls);
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc)
 #pragma unroll
@@ -309,8 +315,8 @@ __device__ __forceinline__ void segment(const SegImage& im, int base0, int be, i
   };
   Cursor cl{0, 0};
   if (WIDE) {
-    cl.by = base0 / bw;
-    cl.bx = base0 - cl.by * bw;
+    cl.by = base0 / bwp;
+    cl.bx = base0 - cl.by * bwp;
   }
   Cursor cs = cl;
 #if RKLT_MFMA_RING == 3
@@ -329,8 +335,8 @@ __device__ __forceinline__ void segment(const SegImage& im, int base0, int be, i
   advance(cl);
 #endif
   auto run = [&](u32x2 (&px)[2][2], int base) {
-    const bool valid = q < be - base;
-    const uint32_t od = offset(cs, base, pd, Ld, Wd);
+    const bool valid = q < lanes(cs, base);
+    const uint32_t od = offset(cs, base, pd, Ld);
     mfma_step<R8, PATH>(px, sF, sV, lane, inv, bias, im.rd, od, pd, valid, sxx, sxy);
     advance(cs);
     load(px, cl, base + RKLT_MFMA_RING * stride);
@@ -430,6 +436,7 @@ void rklt_mfma8_kernel(KArgs a) {
     si.ps = __builtin_amdgcn_readfirstlane(im->ps);
     si.pd = __builtin_amdgcn_readfirstlane(im->pd);
     si.bw = __builtin_amdgcn_readfirstlane(im->bw);
+    si.bwp = __builtin_amdgcn_readfirstlane(im->bwp);
     {
       const int H = __builtin_amdgcn_readfirstlane(im->H), W = __builtin_amdgcn_readfirstlane(im->W);
       uint8_t* const dst = im->dst;

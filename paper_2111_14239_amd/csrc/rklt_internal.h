@@ -85,7 +85,8 @@ struct DevImage {
   int32_t bw, nblocks, tile0, ntiles;
   int32_t slot;            // index of this image's rklt_result
   int32_t tile_blocks;     // blocks per tile (the image has ntiles <= 65535 tiles)
-  int32_t pad[2];
+  int32_t bwp;             // blocks per row of the block index space (see mfma8_pad_rows)
+  int32_t pad;
 };
 
 struct KArgs {
@@ -101,6 +102,17 @@ struct KArgs {
 
 // Number of anti-diagonals i + j < D that contain the first r zig-zag
 // positions of an N x N block.
+// The matrix-core kernel codes 32 consecutive blocks of one block row per
+// wave step.  Images at least 32 blocks wide get a block index space whose
+// rows are padded to a multiple of 32 blocks, so that no step straddles two
+// block rows (a straddling step splits every load and store into short
+// pieces, which costs about a third of the bandwidth); the padding blocks are
+// never loaded or stored.  Narrower images keep their own width.
+inline void mfma8_pad_rows(DevImage& d) {
+  d.bwp = d.bw >= 32 ? (d.bw + 31) / 32 * 32 : d.bw;
+  d.nblocks = (d.H / 8) * d.bwp;
+}
+
 // Inverse form of the matrix-core kernel for r kept coefficients (see
 // DevTransform): 1 and 3 exact, 2 FP32.
 __host__ __device__ inline int mfma8_path(const DevTransform& t, int r) {
