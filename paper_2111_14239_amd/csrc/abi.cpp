@@ -547,6 +547,8 @@ namespace {
 // a full-chip launch, measured on MI355X with batches of one form and one R8.
 // Form 1 is bound by memory up to 32 coefficients; forms 3 and 2 (two
 // accumulators; eight 32x32x2 products per chunk) by the matrix cores.
+constexpr double kMfma8ImageCost = 150 * 22.2;
+
 double mfma8_block_cost(int path, int r) {
   static const double form1[8] = {22.3, 21.9, 22.1, 22.2, 22.9, 24.4, 26.2, 26.9};
   const int R8 = (r + 7) / 8;
@@ -603,8 +605,12 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
       for (int t = 0; t < imgs[k].ntiles; ++t) {
         const int64_t b0 = static_cast<int64_t>(t) * imgs[k].tile_blocks;
         const int64_t nb = std::min<int64_t>(imgs[k].tile_blocks, imgs[k].nblocks - b0);
-        cost[imgs[k].tile0 + t] = c * static_cast<double>(nb);
-        sum += c * static_cast<double>(nb);
+        // each image also costs a fixed set-up (operands, ring fill, final
+        // reduction): about as much as 150 blocks, measured with batches of
+        // thousands of 64 x 64 and 128 x 128 images
+        const double c_t = c * static_cast<double>(nb) + (t == 0 ? kMfma8ImageCost : 0.0);
+        cost[imgs[k].tile0 + t] = c_t;
+        sum += c_t;
       }
     }
     wg_tiles.assign(static_cast<size_t>(q->grid) + 1, static_cast<int32_t>(total));
