@@ -33,6 +33,7 @@ struct PlanPart {
   int grid = 0;
   size_t off_imgs = 0, off_tile_img = 0, off_wg_tiles = 0;
   bool has_wg_tiles = false;
+  bool bigt = false;  // panel kernel: some transform has entries beyond int8
 };
 
 struct rklt_plan {
@@ -65,8 +66,8 @@ constexpr int kDefaultWg = 256;
 constexpr int kDefaultBpt = 4;
 
 // Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
-// 0 = generic LDS kernel.  Coefficient dumps are written by the register and
-// generic kernels.
+// 0 = panel kernel (any N, any level shift).  Coefficient dumps are written
+// by the register and panel kernels.
 int kernel_class(const DevTransform& t, int ell, bool dump);
 
 bool block8_fits(const DevTransform& t, int ell) {
@@ -317,6 +318,15 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
     }
     dt.sig[i] = sig;
   }
+  for (int i = 0; i < N; ++i)
+    for (int m = 0; m < N; ++m) dt.Gt[i * N + m] = dt.G[m * N + i];
+  if (max_abs <= 127)
+    for (int j = 0; j < N; ++j)
+      for (int w = 0; w < N / 4; ++w) {
+        uint32_t word = 0;
+        for (int e = 0; e < 4; ++e) word |= (static_cast<uint32_t>(t->T[j * N + 4 * w + e]) & 0xffu) << (8 * e);
+        dt.Tw[j * (N / 4) + w] = static_cast<int32_t>(word);
+      }
   if (N == 8) {
     // Exact inverse for the N = 8 register kernel, with the bounds that keep
     // every inverse stage exact in FP32: |B_ij| <= 128 L1_i L1_j (pixels - 128
@@ -521,12 +531,15 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     if ((st = check_image(ctx, *img, 0, &a.one, &N))) return st;
     a.dump = (img->coef_out || img->scaled_out) ? 1 : 0;
     const int cls = kernel_class(ctx->host[img->transform_id], img->level_shift, a.dump != 0);
+    const bool bigt = ctx->host[img->transform_id].max_abs > 127;
+    const int PB = panel_blocks(N);
     if (cls == 2) mfma8_pad_rows(a.one);
+    if (cls == 0) panel_pad_rows(a.one, PB, N);
     a.one.tile0 = 0;
     a.one.slot = 0;
     a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
                         : cls == 1 ? image_tile_blocks(a.one, wg * bpt, wg)
-                                   : image_tile_blocks(a.one, generic_blocks_per_tile(N), generic_blocks_per_iteration(N));
+                                   : image_tile_blocks(a.one, 4 * PB, 4 * PB);
     a.one.ntiles = (a.one.nblocks + a.one.tile_blocks - 1) / a.one.tile_blocks;
     a.total_tiles = a.one.ntiles;
     a.tf = ctx->d_table;
@@ -536,7 +549,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int grid = a.total_tiles;
     return cls == 2 ? launch_mfma8(a, grid, wg, stream)
            : cls == 1 ? launch_block8(a, grid, wg, stream)
-                      : launch_generic(N, a, grid, stream);
+                      : launch_panel(N, a, grid, bigt, stream);
   }
 }
 
@@ -564,10 +577,17 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int N,
                        PlanPart* q, std::vector<unsigned char>& img) {
   const bool b8 = cls > 0;
-  const int base = cls == 2 ? (wg / 2) * bpt : b8 ? wg * bpt : generic_blocks_per_tile(N);
-  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : generic_blocks_per_iteration(N);
+  // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds
+  const int PB = panel_blocks(N);
+  const int base = cls == 2 ? (wg / 2) * bpt : b8 ? wg * bpt : 64 * PB;
+  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : 4 * PB;
+  q->bigt = false;
   int64_t total = 0;
   for (auto& d : imgs) {
+    if (cls == 0) {
+      panel_pad_rows(d, PB, N);
+      if (ctx->host[d.tid].max_abs > 127) q->bigt = true;
+    }
     d.tile0 = static_cast<int32_t>(total);
     d.tile_blocks = image_tile_blocks(d, base, unit);
     d.ntiles = (d.nblocks + d.tile_blocks - 1) / d.tile_blocks;
@@ -878,7 +898,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.dump = p->dump ? 1 : 0;
     const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
                            : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
-                                        : launch_generic(p->N, a, q.grid, stream);
+                                        : launch_panel(p->N, a, q.grid, q.bigt, stream);
     if (st) return st;
   }
   return RKLT_OK;

@@ -3,7 +3,8 @@
 // zig-zag zonal truncation in FP32, inverse with T_hat^-1 in FP32, rounding
 // floor(x + 1/2), clipping, and the per-image squared error with PSNR.
 //
-// Two block kernels share the tile / result protocol:
+// The register kernel below shares the tile / result protocol with the
+// matrix-core kernel (codec_mfma.hip) and the panel kernel (codec_panel.hip):
 //   * rklt_block8_kernel: N = 8, level shift 128, int8-range T.  One thread codes whole
 //     8 x 8 blocks in registers: pixels arrive as two 32-bit words per row
 //     (coalesced across the wave: 64 lanes read 512 contiguous bytes per
@@ -12,8 +13,6 @@
 //     anti-diagonals i + j < D that hold kept coefficients are computed
 //     (D is a template parameter), so truncation removes work instead of
 //     masking it.
-//   * rklt_generic_kernel<N>: any N in {4, 8, 16, 32}; blocks staged in LDS,
-//     one output entry per thread and stage, int32 forward.
 //
 // Work list: a tile is a run of consecutive blocks of one image.  A
 // workgroup loops over tiles (persistent grid for a plan, one tile per
@@ -200,133 +199,6 @@ __global__ __launch_bounds__(256) void rklt_block8_kernel(KArgs a) {
   }
 }
 
-// Blocks per inner iteration and pixels per thread of the generic kernel
-// (256 threads).
-template <int N>
-struct GenericShape {
-  static constexpr int NN = N * N;
-  static constexpr int BPI = NN >= 256 ? 1 : 256 / NN;
-  static constexpr int PPT = NN >= 256 ? NN / 256 : 1;
-  static constexpr int ITEMS = BPI * NN;
-  static constexpr int TILE_BLOCKS = 4096 / NN;  // 4096 pixels per tile
-};
-
-template <int N, bool PLAN>
-__global__ __launch_bounds__(256) void rklt_generic_kernel(KArgs a) {
-  using S = GenericShape<N>;
-  constexpr int NN = S::NN, BPI = S::BPI, PPT = S::PPT, ITEMS = S::ITEMS;
-  __shared__ int sX[ITEMS];
-  __shared__ int sY[ITEMS];
-  __shared__ float sC[ITEMS];
-  __shared__ float sW[ITEMS];
-  __shared__ int sT[NN];
-  __shared__ float sG[NN];
-  __shared__ float sw[NN];
-  __shared__ int srank[NN];
-  __shared__ unsigned long long red[4];
-  int loaded = -1;
-  for (int tile = tile_begin(a.total_tiles); tile < tile_end_of(a.total_tiles); ++tile) {
-    const int ii = PLAN ? a.tile_img[tile] : 0;
-    const DevImage* im = PLAN ? a.imgs + ii : &a.one;
-    const DevTransform* tf = a.tf + im->tid;
-    if (im->tid != loaded) {
-      __syncthreads();
-      for (int k = threadIdx.x; k < NN; k += blockDim.x) {
-        sT[k] = tf->T[k];
-        sG[k] = tf->G[k];
-        sw[k] = tf->w[k];
-        srank[k] = tf->rank[k];
-      }
-      __syncthreads();
-      loaded = im->tid;
-    }
-    const int tile_blocks = im->tile_blocks;
-    const int b0 = (tile - im->tile0) * tile_blocks;
-    const int nblocks = im->nblocks, bw = im->bw, r = im->r, ell = im->ell;
-    const float base = static_cast<float>(ell) + 0.5f;
-    unsigned long long sse = 0;
-    for (int it = 0; it * BPI < tile_blocks; ++it) {
-      const int bbase = b0 + it * BPI;
-      if (bbase >= nblocks) break;
-      int orig[PPT];
-      // pixels: entry (q, m, n) = idx -> block bbase + q, row m, column n
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int idx = threadIdx.x + e * 256;
-        const int q = idx / NN, pos = idx % NN, m = pos / N, n = pos % N;
-        const int b = bbase + q;
-        int v = 0;
-        orig[e] = 0;
-        if (b < nblocks) {
-          const int by = b / bw, bx = b - by * bw;
-          const int p = im->src[static_cast<size_t>(by * N + m) * im->ps + bx * N + n];
-          orig[e] = p;
-          v = p - ell;
-        }
-        sX[idx] = v;
-      }
-      __syncthreads();
-      // rows: Y[q][m][j] = sum_n X[q][m][n] T[j][n]
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int idx = threadIdx.x + e * 256;
-        const int q = idx / NN, pos = idx % NN, m = pos / N, j = pos % N;
-        int y = 0;
-#pragma unroll 8
-        for (int n = 0; n < N; ++n) y += sX[q * NN + m * N + n] * sT[j * N + n];
-        sY[idx] = y;
-      }
-      __syncthreads();
-      // columns: B[q][i][j] = sum_m T[i][m] Y[q][m][j]; scale and keep
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int idx = threadIdx.x + e * 256;
-        const int q = idx / NN, pos = idx % NN, i = pos / N, j = pos % N;
-        int B = 0;
-#pragma unroll 8
-        for (int m = 0; m < N; ++m) B += sT[i * N + m] * sY[q * NN + m * N + j];
-        const int b = bbase + q;
-        if (a.dump && b < nblocks) {
-          if (im->coef) im->coef[static_cast<size_t>(b) * NN + pos] = B;
-          if (im->scaled) im->scaled[static_cast<size_t>(b) * NN + pos] = static_cast<float>(B) * sw[pos];
-        }
-        sC[idx] = srank[pos] < r ? static_cast<float>(B) * sw[pos] : 0.0f;
-      }
-      __syncthreads();
-      // inverse, columns: W[q][m][j] = sum_i G[m][i] Bh[q][i][j]
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int idx = threadIdx.x + e * 256;
-        const int q = idx / NN, pos = idx % NN, m = pos / N, j = pos % N;
-        float w = 0.0f;
-#pragma unroll 8
-        for (int i = 0; i < N; ++i) w = fmaf(sG[m * N + i], sC[q * NN + i * N + j], w);
-        sW[idx] = w;
-      }
-      __syncthreads();
-      // inverse, rows: A[q][m][n] = ell + 1/2 + sum_j W[q][m][j] G[n][j]
-#pragma unroll
-      for (int e = 0; e < PPT; ++e) {
-        const int idx = threadIdx.x + e * 256;
-        const int q = idx / NN, pos = idx % NN, m = pos / N, n = pos % N;
-        float acc = base;
-#pragma unroll 8
-        for (int j = 0; j < N; ++j) acc = fmaf(sW[q * NN + m * N + j], sG[n * N + j], acc);
-        const int b = bbase + q;
-        if (b < nblocks) {
-          const int v = static_cast<int>(__builtin_amdgcn_fmed3f(floorf(acc), 0.0f, 255.0f));
-          const int by = b / bw, bx = b - by * bw;
-          if (im->dst) im->dst[static_cast<size_t>(by * N + m) * im->pd + bx * N + n] = static_cast<uint8_t>(v);
-          const int diff = orig[e] - v;
-          sse += static_cast<unsigned long long>(diff * diff);
-        }
-      }
-      __syncthreads();
-    }
-    reduce_and_finish(sse, red, a.res + im->slot, 1, im->ntiles, static_cast<long long>(im->H) * im->W);
-  }
-}
-
 __global__ __launch_bounds__(256) void rklt_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                         size_t n) {
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
@@ -341,49 +213,11 @@ rklt_status launched(const char* what) {
 
 }  // namespace
 
-int generic_blocks_per_iteration(int N) {
-  switch (N) {
-    case 4: return GenericShape<4>::BPI;
-    case 8: return GenericShape<8>::BPI;
-    case 16: return GenericShape<16>::BPI;
-    case 32: return GenericShape<32>::BPI;
-    default: return 0;
-  }
-}
-
-int generic_blocks_per_tile(int N) {
-  switch (N) {
-    case 4: return GenericShape<4>::TILE_BLOCKS;
-    case 8: return GenericShape<8>::TILE_BLOCKS;
-    case 16: return GenericShape<16>::TILE_BLOCKS;
-    case 32: return GenericShape<32>::TILE_BLOCKS;
-    default: return 0;
-  }
-}
-
 rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream) {
   const hipStream_t st = static_cast<hipStream_t>(stream);
   if (a.imgs) hipLaunchKernelGGL(rklt_block8_kernel<true>, dim3(grid), dim3(wg), 0, st, a);
   else hipLaunchKernelGGL(rklt_block8_kernel<false>, dim3(grid), dim3(wg), 0, st, a);
   return launched("rklt_block8_kernel");
-}
-
-template <int N>
-void launch_generic_n(const KArgs& a, int grid, hipStream_t st) {
-  if (a.imgs) hipLaunchKernelGGL((rklt_generic_kernel<N, true>), dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL((rklt_generic_kernel<N, false>), dim3(grid), dim3(256), 0, st, a);
-}
-
-rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream) {
-  const hipStream_t st = static_cast<hipStream_t>(stream);
-  switch (N) {
-    case 4: launch_generic_n<4>(a, grid, st); break;
-    case 8: launch_generic_n<8>(a, grid, st); break;
-    case 16: launch_generic_n<16>(a, grid, st); break;
-    case 32: launch_generic_n<32>(a, grid, st); break;
-    default: return fail(RKLT_E_INVAL, "generic kernel: N=%d not supported", N);
-  }
-  return launched("rklt_generic_kernel");
 }
 
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream) {

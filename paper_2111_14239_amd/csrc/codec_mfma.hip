@@ -63,12 +63,6 @@ typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// The plan's work list is written before the launch and only read by the
-// kernel: constant-address-space reads become scalar loads that no pixel
-// store can invalidate.
-typedef const __attribute__((address_space(4))) DevImage* ConstImage;
-typedef const __attribute__((address_space(4))) int32_t* ConstInt;
-
 // Exact fp16 halves of four int32 coefficients (|B| < 32768): hi = B rounded
 // toward zero to fp16, lo = B - hi (|lo| < 16, an exact fp16 integer).  The
 // words are [hi0 hi1] [lo0 lo1] [hi2 hi3] [lo2 lo3]; lo comes from one

@@ -24,6 +24,12 @@ __device__ __forceinline__ ConstTransform as_constant(const DevTransform* p) {
   return (ConstTransform)(p);
 }
 
+// The plan's work list is written before the launch and only read by the
+// kernels: constant-address-space reads become scalar loads that no pixel
+// store can invalidate, and the values they give are wave-uniform.
+typedef const __attribute__((address_space(4))) DevImage* ConstImage;
+typedef const __attribute__((address_space(4))) int32_t* ConstInt;
+
 // Image pointers always address global memory; saying so gives global_load /
 // global_store instead of flat accesses.
 template <typename T>

@@ -71,6 +71,11 @@ struct alignas(256) DevTransform {
   float Ti[RKLT_MAX_N * RKLT_MAX_N];    // T^-1 = T_hat^-1 S at m*N + i
   int32_t T[RKLT_MAX_N * RKLT_MAX_N];   // T at i*N + j
   int32_t rank[RKLT_MAX_N * RKLT_MAX_N];  // zig-zag position of (i, j)
+  // panel kernel (read as wave-uniform scalars): rows of T as int8x4 words
+  // (word j * N / 4 + w holds T[j][4w .. 4w + 3]; all zero when some
+  // |T| > 127) and T_hat^-1 transposed (Gt[i * N + m] = G[m * N + i])
+  int32_t Tw[RKLT_MAX_N * RKLT_MAX_N / 4];
+  float Gt[RKLT_MAX_N * RKLT_MAX_N];
 };
 
 // One image of a launch (device memory for a plan, a kernel argument for the
@@ -100,8 +105,6 @@ struct KArgs {
   DevImage one;               // the image of the plain path
 };
 
-// Number of anti-diagonals i + j < D that contain the first r zig-zag
-// positions of an N x N block.
 // The matrix-core kernel codes 32 consecutive blocks of one block row per
 // wave step.  Images at least 32 blocks wide get a block index space whose
 // rows are padded to a multiple of 32 blocks, so that no step straddles two
@@ -113,12 +116,22 @@ inline void mfma8_pad_rows(DevImage& d) {
   d.nblocks = (d.H / 8) * d.bwp;
 }
 
+// The panel kernel codes PB = panel_blocks(N) consecutive blocks of one
+// block row per wave step: block rows are padded to a multiple of PB blocks
+// in its block index space (the padding is never loaded or stored).
+inline void panel_pad_rows(DevImage& d, int PB, int N) {
+  d.bwp = (d.bw + PB - 1) / PB * PB;
+  d.nblocks = (d.H / N) * d.bwp;
+}
+
 // Inverse form of the matrix-core kernel for r kept coefficients (see
 // DevTransform): 1 and 3 exact, 2 FP32.
 __host__ __device__ inline int mfma8_path(const DevTransform& t, int r) {
   return r <= t.m_r1 ? 1 : t.m_path3 ? 3 : 2;
 }
 
+// Number of anti-diagonals i + j < D that contain the first r zig-zag
+// positions of an N x N block.
 inline int diagonals_for(int N, int r) {
   int D = 0, covered = 0;
   while (covered < r) {
@@ -132,10 +145,9 @@ inline int diagonals_for(int N, int r) {
 rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream);
 rklt_status launch_mfma8(const KArgs& a, int grid, int wg, void* stream);
 int mfma8_resident_wgs_per_cu(int wg);
-rklt_status launch_generic(int N, const KArgs& a, int grid, void* stream);
+rklt_status launch_panel(int N, const KArgs& a, int grid, bool bigt, void* stream);
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
-int generic_blocks_per_tile(int N);
-int generic_blocks_per_iteration(int N);
+int panel_blocks(int N);  // blocks of one panel of the panel kernel
 constexpr int kMaxTilesPerImage = 65535;  // tile count field of the packed accumulator
 
 }  // namespace rklt
