@@ -158,17 +158,19 @@ def _time_plan(plan, res, stream, steps: int) -> float:
 
 
 def uneven(ctx, steps: int) -> dict:
-    """The uneven batch: 2000 AR(1) images of mixed sizes in one persistent
-    launch, with the library's default tiling and after its autotuner."""
+    """The uneven batch: 2000 AR(1) images of mixed sizes (pitched: rows on
+    128-byte boundaries) in one persistent launch, with the library's default
+    tiling and after its autotuner."""
     import torch
 
     from paper_2111_14239_amd import rklt
     from paper_2111_14239_amd.inputs import uneven_batch
 
     specs = uneven_batch(UNEVEN_IMAGES)
+    # pitched images: rows start on 128-byte boundaries
     with ProcessPoolExecutor(max_workers=WORKERS) as ex:
-        srcs = [torch.from_numpy(a).to("cuda") for a in ex.map(_gen, specs, chunksize=8)]
-    dsts = [torch.empty_like(x) for x in srcs]
+        srcs = [rklt.to_pitched(a) for a in ex.map(_gen, specs, chunksize=8)]
+    dsts = [rklt.empty_pitched(s.H, s.W) for s in specs]
     descs = [rklt.image_desc(x, ctx.transform_id(8, s.rho, s.alpha), s.r, dst=d)
              for x, d, s in zip(srcs, dsts, specs)]
     pixels = sum(s.H * s.W for s in specs)

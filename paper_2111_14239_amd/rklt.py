@@ -191,6 +191,28 @@ def make_tuning(wg_threads=0, blocks_per_thread=0, grid_wgs=0):
     return Tuning(int(wg_threads), int(blocks_per_thread), int(grid_wgs), 0)
 
 
+ROW_ALIGN = 128
+
+
+def empty_pitched(H: int, W: int, device="cuda"):
+    """An uninitialised H x W uint8 device image whose rows start on 128-byte
+    boundaries (pitch = W rounded up to 128): the layout the kernels read and
+    write fastest, since no cache line of a row is shared with the next.
+    Any pitch that is a multiple of 8 is accepted by the library."""
+    import torch
+    P = (int(W) + ROW_ALIGN - 1) // ROW_ALIGN * ROW_ALIGN
+    return torch.empty((int(H), P), dtype=torch.uint8, device=device)[:, :int(W)]
+
+
+def to_pitched(img, device="cuda"):
+    """Copy a 2D uint8 array (numpy or torch) into a new pitched device image."""
+    import torch
+    t = torch.as_tensor(img)
+    out = empty_pitched(t.shape[0], t.shape[1], device)
+    out.copy_(t, non_blocking=False)
+    return out
+
+
 def new_results(n: int, device="cuda"):
     """A zero-filled device array of n rklt_result (uint8 tensor of n*32 bytes)."""
     import torch

@@ -150,7 +150,7 @@ class Server:
         reqs = sorted(requests, key=lambda q: q.arrival)
         for req in reqs:
             W = int(req.src.shape[1])
-            req._pitch = (W + 7) // 8 * 8
+            req._pitch = (W + rklt.ROW_ALIGN - 1) // rklt.ROW_ALIGN * rklt.ROW_ALIGN  # rows on 128-byte boundaries
             if req.tid < 0:
                 try:
                     req.tid = self.ctx.transform_id(req.N, req.rho, req.alpha)

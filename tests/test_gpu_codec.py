@@ -492,3 +492,28 @@ def test_autotune_keeps_results_and_rejects_bad_arguments(ctx):
     torch.cuda.synchronize()
     assert [(q["sse"], q["psnr_db"]) for q in rklt.read_results(res)] == before
     plan.close()
+
+
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_precision_of_the_fp32_inverse(ctx, N):
+    # the panel kernel's FP32 inverse against the oracle's FP64 / exact
+    # rational reconstruction, on 256 x 256 AR(1) images (level shift 37 puts
+    # N = 8 on that kernel too): pixels that differ are all within the tie
+    # band, the share that differs is small, and the PSNR moves by at most
+    # what those pixels allow.  The figures are printed (run with -s).
+    rho = 0.9
+    a = alpha8(N, rho) if N != 8 else 2.0
+    ell = 37 if N == 8 else 128
+    stats = []
+    for r in sorted({1, max(1, (10 * N * N + 63) // 64), N * N // 4, N * N}):
+        img = ar1_image(256, 256, rho, seed=500 + N + r)
+        got = run_plain(ctx, img, N, rho, a, r, ell=ell)
+        ref = check_against_oracle(img, N, rho, a, r, ell, got)
+        diff = got["recon"].astype(np.int64) - ref["recon"].astype(np.int64)
+        frac = ref["pre_round"] - np.floor(ref["pre_round"])
+        off = int(np.count_nonzero(diff))
+        stats.append((r, off / diff.size, float(np.max(np.abs(frac - 0.5)[diff != 0], initial=0.0)),
+                      abs(got["psnr_db"] - ref["psnr"])))
+        assert off / diff.size <= 2e-3
+    print(f"\nN={N}: (r, share of pixels off by one, largest |x - tie| among them, |dPSNR| dB)",
+          [(r, f"{s:.2e}", f"{t:.1e}", f"{p:.1e}") for r, s, t, p in stats])
