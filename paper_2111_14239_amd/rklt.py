@@ -373,3 +373,50 @@ def codec_image(ctx: Context, img, rho: float, alpha: float, r: int, level_shift
     desc = image_desc(img, tid, r, dst=dst, level_shift=level_shift, coef_out=coef, scaled_out=scaled)
     ctx.codec(desc, _ptr(res), tuning, stream)
     return dst, res, coef, scaled
+
+
+_default_ctx: dict = {}
+
+
+def _ctx_for(device) -> Context:
+    import torch
+    dev = torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _default_ctx:
+        _default_ctx[idx] = Context(idx)
+    return _default_ctx[idx]
+
+
+def codec(img, rho: float, alpha: float, r: int, level_shift: int = 128, N: int = 8, ctx: Context | None = None):
+    """Code one device uint8 image (2D tensor) on the plain path and wait:
+    returns (reconstruction tensor, SSE, PSNR in dB)."""
+    import torch
+    ctx = ctx or _ctx_for(img.device)
+    dst, res, _, _ = codec_image(ctx, img, rho, alpha, r, level_shift=level_shift, N=N)
+    torch.cuda.current_stream(img.device).synchronize()
+    out = read_results(res)[0]
+    return dst, out["sse"], out["psnr_db"]
+
+
+def codec_batch(images, params, ctx: Context | None = None, tuning: Tuning | None = None):
+    """Code a list of device uint8 images in one batched launch per kernel
+    class and wait.  params[i] = (rho, alpha, r) or (rho, alpha, r,
+    level_shift, N).  Returns (reconstructions, list of result dicts)."""
+    import torch
+    if not images:
+        return [], []
+    ctx = ctx or _ctx_for(images[0].device)
+    dsts, descs = [], []
+    for img, p in zip(images, params):
+        rho, alpha, r = p[0], p[1], p[2]
+        ell = p[3] if len(p) > 3 else 128
+        N = p[4] if len(p) > 4 else 8
+        d = torch.empty_like(img)
+        dsts.append(d)
+        descs.append(image_desc(img, ctx.transform_id(N, rho, alpha), r, dst=d, level_shift=ell))
+    res = new_results(len(images), images[0].device)
+    plan = ctx.plan(descs, tuning)
+    plan.run(_ptr(res))
+    torch.cuda.current_stream(images[0].device).synchronize()
+    plan.close()
+    return dsts, read_results(res)

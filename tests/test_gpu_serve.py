@@ -118,3 +118,16 @@ def test_server_rejects_requests_larger_than_the_arena(ctx):
         if q is not big:
             _, alone = plain(ctx, q.src, q.rho, q.alpha, q.r)
             assert q.result["sse"] == alone["sse"]
+
+
+def test_convenience_codec_and_codec_batch(ctx):
+    imgs = [torch.from_numpy(ar1_image(H, W, 0.9, 70 + k)).cuda() for k, (H, W) in enumerate([(64, 64), (136, 264)])]
+    rec, sse, psnr = rklt.codec(imgs[0], 0.9, 2.0, 10, ctx=ctx)
+    d, res, _, _ = rklt.codec_image(ctx, imgs[0], 0.9, 2.0, 10)
+    torch.cuda.synchronize()
+    assert torch.equal(rec, d) and sse == rklt.read_results(res)[0]["sse"]
+    recs, results = rklt.codec_batch(imgs, [(0.9, 2.0, 10), (0.5, 3.0, 33, 128, 8)], ctx=ctx)
+    assert torch.equal(recs[0], rec) and results[0]["sse"] == sse and results[0]["psnr_db"] == psnr
+    d1, res1, _, _ = rklt.codec_image(ctx, imgs[1], 0.5, 3.0, 33)
+    torch.cuda.synchronize()
+    assert torch.equal(recs[1], d1) and results[1]["sse"] == rklt.read_results(res1)[0]["sse"]
