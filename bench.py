@@ -141,9 +141,31 @@ UNEVEN_IMAGES = 2000
 WORKERS = min(16, os.cpu_count() or 1)
 
 
+WARM_MS = 40.0
+
+
+def _warm(run, stream, ms: float = WARM_MS):
+    """Keep the GPU busy with `run` for about `ms` milliseconds: its clocks
+    ramp up over the first ~10-20 ms of sustained load (the first hundred
+    launches of the batch run ~15% slower), so a timed region that starts
+    cold measures the ramp instead of the kernel."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    run()
+    b.record(stream)
+    torch.cuda.synchronize()
+    one = max(a.elapsed_time(b), 1e-3)
+    for _ in range(int(ms / one) + 1):
+        run()
+    torch.cuda.synchronize()
+
+
 def _time_plan(plan, res, stream, steps: int) -> float:
     """Milliseconds per launch over `steps` back-to-back launches."""
     import torch
+    _warm(lambda: plan.run(int(res.data_ptr()), stream), stream)
     for _ in range(3):
         plan.run(int(res.data_ptr()), stream)
     a = torch.cuda.Event(enable_timing=True)
@@ -206,8 +228,7 @@ def single(ctx, steps: int) -> dict:
     res = rklt.new_results(1)
     desc = rklt.image_desc(x, ctx.transform_id(s.N, s.rho, s.alpha), s.r, dst=d, level_shift=s.ell)
     stream = torch.cuda.current_stream()
-    for _ in range(10):
-        ctx.codec(desc, int(res.data_ptr()), None, stream)
+    _warm(lambda: ctx.codec(desc, int(res.data_ptr()), None, stream), stream)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     for a, b in ev:
@@ -264,8 +285,9 @@ def block_sizes(ctx, steps: int) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed launches first (about 40 ms of load, past the GPU's clock ramp)")
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--images", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
