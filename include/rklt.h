@@ -206,6 +206,18 @@ rklt_status rklt_plan_run(rklt_plan* plan, rklt_result* d_res, void* stream);
  * previous tuning (or holds no images if re-tiling failed). */
 rklt_status rklt_plan_autotune(rklt_plan* plan, rklt_result* d_res, int32_t reps, void* stream,
                                rklt_tuning* chosen);
+/* Mean structural similarity of every image's reconstruction against its
+ * source, the paper's third quality measure (§4.1, the SSIM of Wang et al.
+ * 2004): an 11 x 11 Gaussian window with standard deviation 1.5, C1 =
+ * (0.01 * 255)^2, C2 = (0.03 * 255)^2, evaluated at every window position
+ * inside the image and averaged.  Reads src and dst of the plan's images, so
+ * it belongs after rklt_plan_run on the same stream.  d_mssim: n device
+ * doubles in the order of the plan's images; NaN for an image without a
+ * reconstruction or with a side below 11.  FP32 window sums, double
+ * accumulation in a fixed order (deterministic).  Two launches; no
+ * allocation (the per-tile sums live in the plan's device buffer).
+ * Errors: E_INVAL (NULL plan or d_mssim), E_STATE (empty plan), E_HIP. */
+rklt_status rklt_plan_mssim(rklt_plan* plan, double* d_mssim, void* stream);
 /* Replace the plan's images with `n` new ones (same rules as
  * rklt_plan_create; the tuning given at creation is kept) without a
  * synchronous copy: the work list is rebuilt on the host and uploaded with an

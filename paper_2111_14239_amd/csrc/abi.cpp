@@ -55,6 +55,9 @@ struct rklt_plan {
   size_t h_cap = 0;
   // the caller's descriptors of the current images (for re-tiling)
   std::vector<rklt_image> images;
+  // MSSIM work list (records in the device buffer, then the per-tile sums)
+  size_t off_ms = 0, off_partials = 0, d_need = 0;
+  int ms_total = 0;
 };
 
 namespace rklt {
@@ -700,11 +703,38 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
     if (st) return st;
     ++p->nparts;
   }
+  // MSSIM tiles of every image with a reconstruction, in slot order
+  std::vector<MsImage> ms(static_cast<size_t>(n));
+  int64_t ms_total = 0;
+  for (int k = 0; k < n; ++k) {
+    MsImage& m = ms[k];
+    std::memset(&m, 0, sizeof(m));
+    m.x = imgs[k].src;
+    m.y = imgs[k].dst;
+    m.H = imgs[k].H;
+    m.W = imgs[k].W;
+    m.px = imgs[k].pitch_src;
+    m.py = imgs[k].dst ? imgs[k].pitch_dst : 0;
+    m.slot = k;
+    m.tile0 = static_cast<int32_t>(ms_total);
+    if (imgs[k].dst && m.H >= 11 && m.W >= 11) {
+      m.across = (m.W - 10 + kMsTileW - 1) / kMsTileW;
+      m.ntiles = m.across * ((m.H - 10 + kMsTileH - 1) / kMsTileH);
+    }
+    ms_total += m.ntiles;
+  }
+  if (ms_total >= (int64_t{1} << 31)) return fail(RKLT_E_INVAL, "rklt_plan: too many MSSIM tiles");
+  p->ms_total = static_cast<int>(ms_total);
+  p->off_ms = align256(p->h_image.size());
+  p->h_image.resize(p->off_ms + sizeof(MsImage) * ms.size());
+  std::memcpy(p->h_image.data() + p->off_ms, ms.data(), sizeof(MsImage) * ms.size());
+  p->off_partials = align256(p->h_image.size());
+  p->d_need = p->off_partials + sizeof(double) * static_cast<size_t>(ms_total);
   return RKLT_OK;
 }
 
 rklt_status ensure_device_capacity(rklt_plan* p) {
-  const size_t need = p->h_image.size();
+  const size_t need = std::max(p->h_image.size(), p->d_need);
   if (need <= p->d_cap) return RKLT_OK;
   (void)hipFree(p->d_buf);
   p->d_buf = nullptr;
@@ -902,6 +932,23 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     if (st) return st;
   }
   return RKLT_OK;
+}
+
+rklt_status rklt_plan_mssim(rklt_plan* p, double* d_mssim, void* stream) {
+  clear_error();
+  if (!p || !d_mssim) return fail(RKLT_E_INVAL, "rklt_plan_mssim: NULL argument");
+  if (p->nparts == 0) return fail(RKLT_E_STATE, "rklt_plan_mssim: the plan holds no images");
+  hipError_t e = use_device(p->ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  unsigned char* base = static_cast<unsigned char*>(p->d_buf);
+  MsArgs a;
+  a.imgs = reinterpret_cast<const MsImage*>(base + p->off_ms);
+  a.partials = reinterpret_cast<double*>(base + p->off_partials);
+  a.out = d_mssim;
+  a.n = p->n;
+  a.total = p->ms_total;
+  const int grid = std::max(1, std::min(p->ms_total, p->ctx->cus * 8));
+  return launch_mssim(a, grid, stream);
 }
 
 rklt_status rklt_plan_destroy(rklt_plan* p) {

@@ -29,6 +29,7 @@ __device__ __forceinline__ ConstTransform as_constant(const DevTransform* p) {
 // store can invalidate, and the values they give are wave-uniform.
 typedef const __attribute__((address_space(4))) DevImage* ConstImage;
 typedef const __attribute__((address_space(4))) int32_t* ConstInt;
+typedef const __attribute__((address_space(4))) MsImage* ConstMsImage;
 
 // Image pointers always address global memory; saying so gives global_load /
 // global_store instead of flat accesses.

@@ -146,6 +146,25 @@ rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream);
 rklt_status launch_mfma8(const KArgs& a, int grid, int wg, void* stream);
 int mfma8_resident_wgs_per_cu(int wg);
 rklt_status launch_panel(int N, const KArgs& a, int grid, bool bigt, void* stream);
+
+// MSSIM of a plan's images (codec_quality.hip): one record per image in
+// slot order, tiles of 32 x 64 window positions numbered image by image.
+struct MsImage {
+  const uint8_t* x;  // source
+  const uint8_t* y;  // reconstruction
+  int32_t H, W, px, py;
+  int32_t tile0, ntiles;  // this image's tiles (0 when it has no reconstruction or is smaller than 11)
+  int32_t across;         // tiles per row of tiles
+  int32_t slot;           // index of the result
+};
+struct MsArgs {
+  const MsImage* imgs;  // n records, tile0 non-decreasing
+  double* partials;     // one sum per tile
+  double* out;          // one MSSIM per image slot
+  int32_t n, total;
+};
+constexpr int kMsTileW = 64, kMsTileH = 32;
+rklt_status launch_mssim(const MsArgs& a, int grid, void* stream);
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
 int panel_blocks(int N);  // blocks of one panel of the panel kernel
 constexpr int kMaxTilesPerImage = 65535;  // tile count field of the packed accumulator

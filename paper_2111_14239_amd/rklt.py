@@ -95,6 +95,7 @@ def _load():
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_ctx_mfma_form": (st, [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
         "rklt_plan_autotune": (st, [vp, vp, C.c_int32, vp, C.POINTER(Tuning)]),
+        "rklt_plan_mssim": (st, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -108,7 +109,7 @@ EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_
             "rklt_ctx_destroy", "rklt_ctx_add_transform", "rklt_codec", "rklt_plan_create",
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
             "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form",
-            "rklt_plan_autotune")
+            "rklt_plan_autotune", "rklt_plan_mssim")
 
 
 def lib():
@@ -341,6 +342,11 @@ class Plan:
                                        C.c_void_p(_stream_handle(stream)), C.byref(t)))
         self._refresh(self.n)
         return t
+
+    def mssim(self, out_ptr: int, stream=None):
+        """rklt_plan_mssim: MSSIM of every image's reconstruction (n device
+        doubles at out_ptr), after run() on the same stream."""
+        _check(_lib.rklt_plan_mssim(self._h, C.c_void_p(out_ptr), C.c_void_p(_stream_handle(stream))))
 
     def close(self):
         if self._h:

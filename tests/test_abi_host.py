@@ -130,6 +130,7 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert L.rklt_plan_create(None, None, 0, None, C.byref(h)) == rklt.E_INVAL
     assert L.rklt_plan_update(None, None, 0, None) == rklt.E_INVAL
     assert L.rklt_plan_autotune(None, None, 1, None, None) == rklt.E_INVAL
+    assert L.rklt_plan_mssim(None, None, None) == rklt.E_INVAL
     f = C.c_int32()
     assert L.rklt_ctx_mfma_form(None, 0, 1, C.byref(f)) == rklt.E_INVAL
 
