@@ -282,6 +282,35 @@ def block_sizes(ctx, steps: int) -> dict:
     return out
 
 
+SSIM_FLOPS = 2 * 2 * 5 * 11  # per window position: two 11-tap passes of five sums, FMA = 2 flops
+FP32_PEAK_TFLOPS = 157.3
+
+
+def mssim_measure(plan, res, n: int, stream, results) -> dict:
+    """MSSIM of the bench batch's reconstructions (rklt_plan_mssim), timed
+    back to back; ALU-bound, so priced against the FP32 vector peak."""
+    import torch
+    out = torch.zeros(n, dtype=torch.float64, device="cuda")
+    run = lambda: plan.mssim(int(out.data_ptr()), stream)  # noqa: E731
+    _warm(run, stream)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    steps = 20
+    a.record(stream)
+    for _ in range(steps):
+        run()
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    positions = n * (1024 - 10) * (1024 - 10)
+    tflops = SSIM_FLOPS * positions / (ms / 1e3) / 1e12
+    vals = out.cpu().numpy()
+    return {"ms_per_launch": ms, "value": n * 1024 * 1024 / (ms / 1e3) / 1e6, "unit": "Mpixel/s",
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / FP32_PEAK_TFLOPS, "flops_per_window": SSIM_FLOPS},
+            "mean_mssim": float(np.mean(vals)), "min_mssim": float(np.min(vals))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -435,6 +464,8 @@ def main():
         "copy_ceiling_GBps": copy_gbs,
         "mean_psnr_db": float(np.mean([r["psnr_db"] for r in results if np.isfinite(r["psnr_db"])])),
     }
+    if not args.no_extra:
+        line["mssim"] = mssim_measure(plan, res, n, stream, results)
     plan.close()
     del src, dst
     if not args.no_extra:
