@@ -282,6 +282,36 @@ def block_sizes(ctx, steps: int) -> dict:
     return out
 
 
+def comparison_arms(ctx, src, dst, steps: int) -> dict:
+    """The paper's float comparison transforms (the DCT and the exact KLT
+    K_0.8; §4.1, Table 3) and, for reference, the rounded KLT (rho 0.9,
+    alpha 2), all at r = 15 (its figure setting) on the bench batch: one plan
+    each, timed like the main plan.  The float arms run on the panel kernel
+    in FP32; HBM fraction from 2 algorithmic bytes per pixel."""
+    import torch
+
+    from paper_2111_14239_amd import rklt
+
+    n = src.shape[0]
+    pixels = n * src.shape[1] * src.shape[2]
+    res = rklt.new_results(n)
+    stream = torch.cuda.current_stream()
+    out = {}
+    arms = (("dct", ctx.float_transform_id("dct", 8)), ("klt_rho0.8", ctx.float_transform_id("klt", 8, 0.8)),
+            ("rklt_rho0.9_alpha2", ctx.transform_id(8, 0.9, 2.0)))
+    for name, tid in arms:
+        plan = ctx.plan([rklt.image_desc(src[i], tid, 15, dst=dst[i]) for i in range(n)])
+        ms = _time_plan(plan, res, stream, steps)
+        psnr = [r["psnr_db"] for r in rklt.read_results(res)]
+        out[name] = {"ms_per_launch": ms, "value": pixels / (ms / 1e3) / 1e6, "unit": "Mpixel/s",
+                     "hbm_frac": BYTES_PER_PIXEL * pixels / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                     "kernel_class": ("panel_float" if plan.images_per_class[3] else
+                                      "matrix_core_n8" if plan.images_per_class[2] else "other"),
+                     "mean_psnr_db": float(np.mean(psnr))}
+        plan.close()
+    return out
+
+
 SSIM_FLOPS = 2 * 2 * 5 * 11  # per window position: two 11-tap passes of five sums, FMA = 2 flops
 FP32_PEAK_TFLOPS = 157.3
 
@@ -448,7 +478,7 @@ def main():
                         "level shift 128, one persistent launch per step",
             "images": n, "rejected_alpha1": rejected, "pixels": pixels,
             "tiles": plan.tiles, "grid_wgs": plan.grid, "launches_per_step": plan.launches,
-            "images_per_kernel_class": dict(zip(("generic", "register_n8", "matrix_core_n8"),
+            "images_per_kernel_class": dict(zip(("panel", "register_n8", "matrix_core_n8", "panel_float"),
                                                 plan.images_per_class)),
             "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 4,
         },
@@ -467,6 +497,8 @@ def main():
     if not args.no_extra:
         line["mssim"] = mssim_measure(plan, res, n, stream, results)
     plan.close()
+    if not args.no_extra:
+        line["comparison_arms"] = comparison_arms(ctx, src, dst, 50)
     del src, dst
     if not args.no_extra:
         line["single_image"] = single(ctx, 200)

@@ -79,7 +79,8 @@ typedef struct {
 typedef struct {
   const uint8_t* src;   /* H rows of W pixels, row stride pitch_src bytes        */
   uint8_t* dst;         /* reconstruction (same geometry), or NULL: PSNR only    */
-  int32_t* coef_out;    /* optional, verification: int32 B, H*W values          */
+  int32_t* coef_out;    /* optional, verification: int32 B, H*W values (NULL     */
+                        /* for a float transform)                                */
   float* scaled_out;    /* optional, verification: float B_hat, H*W values      */
   int32_t H, W;         /* multiples of N, 1 <= H, W; (H-1)*pitch + W < 2^31     */
   int32_t pitch_src;    /* >= W, multiple of 8 bytes                             */
@@ -138,6 +139,16 @@ rklt_status rklt_build_transform(int32_t N, double rho, double alpha, rklt_trans
  * (caller-owned).  Errors: E_INVAL (N outside 1..32, order NULL). */
 rklt_status rklt_zigzag(int32_t N, int32_t* order);
 
+/* The paper's float comparison transforms (§4.1, Table 3), FP64, N x N
+ * row-major, row k the k-th basis vector; caller-owned output.
+ * rklt_klt_matrix: the exact KLT K_rho of §2.1 (the same K that
+ *   rklt_build_transform returns, for any rho in (0, 1)).
+ * rklt_dct_matrix: the orthonormal DCT-II, C[k][n] = c_k cos(pi (2n+1) k / (2N)),
+ *   c_0 = sqrt(1/N), c_k = sqrt(2/N) for k > 0.
+ * Errors: E_INVAL (N outside 2..32, rho outside (0, 1), NULL output). */
+rklt_status rklt_klt_matrix(int32_t N, double rho, double* K);
+rklt_status rklt_dct_matrix(int32_t N, double* C);
+
 /* ---- device context ----------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  The context owns a device-side
@@ -152,6 +163,21 @@ rklt_status rklt_ctx_destroy(rklt_ctx* ctx);
  * Errors: E_INVAL, E_RANGE (255 * max_row_l1^2 >= 2^31), E_NOMEM (table
  * full), E_HIP. */
 rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32_t* id_out);
+
+/* Upload a float transform M (N x N, FP64, row-major, row k the k-th basis
+ * vector; N in {4, 8, 16, 32}) for the comparison arms of §4.1 / Table 3:
+ * images coded with it take B = M (A - ell) M^T, keep the first r zig-zag
+ * coefficients (no scaling stage), and reconstruct A' = M^-1 B M^-T + ell,
+ * pixel = clip(floor(A' + 1/2), 0, 255).  M^-1 is computed on the host in
+ * FP64 (for an orthonormal M it is M^T up to rounding); the device stores M
+ * and M^-1 in FP32 and codes in FP32 on the panel kernel, so a pixel may
+ * differ by one level from the FP64 result where that result lies within
+ * about 1e-3 (N = 8) of a rounding tie.  An identical M returns the existing
+ * id.  Images of a float transform take no coef_out; scaled_out receives the
+ * FP32 coefficients B.  Errors: E_INVAL (NULL argument, N, an entry not
+ * finite or beyond 1e6), E_SINGULAR (M singular), E_NOMEM (table full),
+ * E_HIP. */
+rklt_status rklt_ctx_add_float_transform(rklt_ctx* ctx, int32_t N, const double* M, int32_t* id_out);
 
 /* Whether the N = 8 register kernel reconstructs transform `id` exactly:
  * T^-1 = adj / den with integer adj small enough that every step of the
@@ -238,8 +264,10 @@ rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_
  *            alpha in {2, 3} but one);
  *   class 1  the N = 8 register kernel: level shift 128, |T_ij| <= 127,
  *            128 * max row L1 <= 32767 (also every plan that dumps coefficients);
- *   class 0  the generic LDS kernel: everything else.
- * Reports the number of launches per run and, in images_per_class[3] (may be
+ *   class 0  the panel kernel (any N, any level shift): every other rounded
+ *            transform;
+ *   class 3  the panel kernel in FP32: float transforms.
+ * Reports the number of launches per run and, in images_per_class[4] (may be
  * NULL), how many images each class codes. */
 rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* images_per_class);
 

@@ -33,8 +33,13 @@ struct PlanPart {
   int grid = 0;
   size_t off_imgs = 0, off_tile_img = 0, off_wg_tiles = 0;
   bool has_wg_tiles = false;
-  bool bigt = false;  // panel kernel: some transform has entries beyond int8
+  int mode = 0;  // panel kernel arithmetic (PanelMode)
 };
+
+// Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
+// 0 = panel kernel (integer T, any N, any level shift), 3 = panel kernel for
+// float transforms.
+constexpr int kClasses = 4;
 
 struct rklt_plan {
   rklt_ctx* ctx = nullptr;
@@ -42,7 +47,7 @@ struct rklt_plan {
   bool dump = false;
   int n = 0;
   int nparts = 0;
-  PlanPart parts[3];
+  PlanPart parts[kClasses];
   int64_t pixels = 0;
   rklt_tuning tuning{};
   bool has_tuning = false;
@@ -68,10 +73,10 @@ thread_local char g_error[512] = "";
 constexpr int kDefaultWg = 256;
 constexpr int kDefaultBpt = 4;
 
-// Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
-// 0 = panel kernel (any N, any level shift).  Coefficient dumps are written
-// by the register and panel kernels.
+// Kernel class of an image (see kClasses).  Coefficient dumps are written by
+// the register and panel kernels.
 int kernel_class(const DevTransform& t, int ell, bool dump);
+bool panel_class(int cls) { return cls == 0 || cls == 3; }
 
 bool block8_fits(const DevTransform& t, int ell) {
   // level shift 128 (pixel xor 0x80), int8 entries for the row dots and
@@ -80,6 +85,7 @@ bool block8_fits(const DevTransform& t, int ell) {
 }
 
 int kernel_class(const DevTransform& t, int ell, bool dump) {
+  if (t.is_float) return 3;
   if (!block8_fits(t, ell)) return 0;
   return (t.m_ok && !dump) ? 2 : 1;
 }
@@ -131,6 +137,8 @@ rklt_status check_image(rklt_ctx* ctx, const rklt_image& im, int index, DevImage
   if (im.level_shift < 0 || im.level_shift > 255)
     return fail(RKLT_E_INVAL, "image %d: level_shift=%d outside 0..255", index, im.level_shift);
   if (im.reserved != 0) return fail(RKLT_E_INVAL, "image %d: reserved field is not 0", index);
+  if (t.is_float && im.coef_out)
+    return fail(RKLT_E_INVAL, "image %d: coef_out (integer coefficients) with a float transform", index);
   DevImage& d = *out;
   std::memset(&d, 0, sizeof(d));
   d.src = im.src;
@@ -317,7 +325,6 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
       dt.T[i * N + j] = t->T[i * N + j];
       dt.w[i * N + j] = static_cast<float>(t->s[i] * t->s[j]);
       dt.G[i * N + j] = static_cast<float>(t->G[i * N + j]);
-      dt.Ti[i * N + j] = static_cast<float>(t->G[i * N + j] * t->s[j]);
     }
     dt.sig[i] = sig;
   }
@@ -381,7 +388,9 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
     dt.den = 0;
     dt.inv_den2 = 1.0f;
     dt.bias = 128.0f + 1.0f / 4096.0f;
-    for (int k = 0; k < 64; ++k) dt.fadj[k] = dt.Ti[k];
+    // T^-1 = T_hat^-1 S in FP32
+    for (int m = 0; m < 8; ++m)
+      for (int i = 0; i < 8; ++i) dt.fadj[m * 8 + i] = static_cast<float>(t->G[m * 8 + i] * t->s[i]);
   }
   if (N == 8 && max_abs * max_abs <= 127) {
     // Matrix-core operands.  The forward weights T_im T_jn fit int8.  The
@@ -496,7 +505,7 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
   std::lock_guard<std::mutex> lock(ctx->mu);
   for (size_t k = 0; k < ctx->host.size(); ++k) {
     const DevTransform& o = ctx->host[k];
-    if (o.N == N && std::memcmp(o.T, dt.T, sizeof(int32_t) * N * N) == 0) {
+    if (!o.is_float && o.N == N && std::memcmp(o.T, dt.T, sizeof(int32_t) * N * N) == 0) {
       *id_out = static_cast<int32_t>(k);
       return RKLT_OK;
     }
@@ -508,6 +517,61 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
   if (e != hipSuccess) return hip_fail("hipSetDevice", e);
   e = hipMemcpy(ctx->d_table + id, &dt, sizeof(dt), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail("rklt_ctx_add_transform: hipMemcpy", e);
+  ctx->host.push_back(dt);
+  *id_out = id;
+  return RKLT_OK;
+}
+
+rklt_status rklt_klt_matrix(int32_t N, double rho, double* K) {
+  clear_error();
+  return klt_matrix(N, rho, K);
+}
+
+rklt_status rklt_dct_matrix(int32_t N, double* C) {
+  clear_error();
+  return dct_matrix(N, C);
+}
+
+rklt_status rklt_ctx_add_float_transform(rklt_ctx* ctx, int32_t N, const double* M, int32_t* id_out) {
+  clear_error();
+  if (!ctx || !M || !id_out) return fail(RKLT_E_INVAL, "rklt_ctx_add_float_transform: NULL argument");
+  if (N != 4 && N != 8 && N != 16 && N != 32)
+    return fail(RKLT_E_INVAL, "rklt_ctx_add_float_transform: N=%d; the codec supports N in {4, 8, 16, 32}", N);
+  for (int k = 0; k < N * N; ++k)
+    if (!std::isfinite(M[k]) || std::fabs(M[k]) > 1e6)
+      return fail(RKLT_E_INVAL, "rklt_ctx_add_float_transform: M[%d]=%g is not finite or beyond 1e6", k, M[k]);
+  double G[RKLT_MAX_N * RKLT_MAX_N];
+  if (!invert_matrix(N, M, G)) return fail(RKLT_E_SINGULAR, "rklt_ctx_add_float_transform: M is singular");
+  DevTransform dt;
+  std::memset(&dt, 0, sizeof(dt));
+  dt.N = N;
+  dt.is_float = 1;
+  int32_t order[RKLT_MAX_N * RKLT_MAX_N];
+  zigzag(N, order);
+  for (int k = 0; k < N * N; ++k) dt.rank[order[k]] = k;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      dt.w[i * N + j] = 1.0f;
+      dt.Mf[i * N + j] = static_cast<float>(M[i * N + j]);
+      dt.G[i * N + j] = static_cast<float>(G[i * N + j]);
+      dt.Gt[j * N + i] = dt.G[i * N + j];
+    }
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  for (size_t k = 0; k < ctx->host.size(); ++k) {
+    const DevTransform& o = ctx->host[k];
+    if (o.is_float && o.N == N && std::memcmp(o.Mf, dt.Mf, sizeof(float) * N * N) == 0 &&
+        std::memcmp(o.Gt, dt.Gt, sizeof(float) * N * N) == 0) {
+      *id_out = static_cast<int32_t>(k);
+      return RKLT_OK;
+    }
+  }
+  if (ctx->host.size() >= static_cast<size_t>(kMaxTransforms))
+    return fail(RKLT_E_NOMEM, "rklt_ctx_add_float_transform: table full (%d transforms)", kMaxTransforms);
+  const int id = static_cast<int>(ctx->host.size());
+  hipError_t e = use_device(ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  e = hipMemcpy(ctx->d_table + id, &dt, sizeof(dt), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail("rklt_ctx_add_float_transform: hipMemcpy", e);
   ctx->host.push_back(dt);
   *id_out = id;
   return RKLT_OK;
@@ -534,10 +598,10 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     if ((st = check_image(ctx, *img, 0, &a.one, &N))) return st;
     a.dump = (img->coef_out || img->scaled_out) ? 1 : 0;
     const int cls = kernel_class(ctx->host[img->transform_id], img->level_shift, a.dump != 0);
-    const bool bigt = ctx->host[img->transform_id].max_abs > 127;
+    const int mode = cls == 3 ? kPanelFloat : ctx->host[img->transform_id].max_abs > 127 ? kPanelBigT : kPanelInt8;
     const int PB = panel_blocks(N);
     if (cls == 2) mfma8_pad_rows(a.one);
-    if (cls == 0) panel_pad_rows(a.one, PB, N);
+    if (panel_class(cls)) panel_pad_rows(a.one, PB, N);
     a.one.tile0 = 0;
     a.one.slot = 0;
     a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
@@ -552,7 +616,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int grid = a.total_tiles;
     return cls == 2 ? launch_mfma8(a, grid, wg, stream)
            : cls == 1 ? launch_block8(a, grid, wg, stream)
-                      : launch_panel(N, a, grid, bigt, stream);
+                      : launch_panel(N, a, grid, mode, stream);
   }
 }
 
@@ -579,17 +643,17 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 // (the plan's host image of the device buffer).
 rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int N,
                        PlanPart* q, std::vector<unsigned char>& img) {
-  const bool b8 = cls > 0;
+  const bool b8 = !panel_class(cls);
   // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds
   const int PB = panel_blocks(N);
   const int base = cls == 2 ? (wg / 2) * bpt : b8 ? wg * bpt : 64 * PB;
   const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : 4 * PB;
-  q->bigt = false;
+  q->mode = cls == 3 ? kPanelFloat : kPanelInt8;
   int64_t total = 0;
   for (auto& d : imgs) {
-    if (cls == 0) {
+    if (!b8) {
       panel_pad_rows(d, PB, N);
-      if (ctx->host[d.tid].max_abs > 127) q->bigt = true;
+      if (cls == 0 && ctx->host[d.tid].max_abs > 127) q->mode = kPanelBigT;
     }
     d.tile0 = static_cast<int32_t>(total);
     d.tile_blocks = image_tile_blocks(d, base, unit);
@@ -664,7 +728,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   int wg, bpt, grid_req;
   rklt_status st = check_tuning(p->has_tuning ? &p->tuning : nullptr, &wg, &bpt, &grid_req);
   if (st) return st;
-  std::vector<DevImage> by_class[3];  // indexed by kernel class
+  std::vector<DevImage> by_class[kClasses];  // indexed by kernel class
   std::vector<DevImage> all;
   int N = 0;
   bool dump = false;
@@ -697,7 +761,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   p->pixels = pixels;
   p->nparts = 0;
   p->h_image.clear();
-  for (int c = 2; c >= 0; --c) {
+  for (int c : {2, 1, 3, 0}) {
     if (by_class[c].empty()) continue;
     st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts], p->h_image);
     if (st) return st;
@@ -928,7 +992,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.dump = p->dump ? 1 : 0;
     const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
                            : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
-                                        : launch_panel(p->N, a, q.grid, q.bigt, stream);
+                                        : launch_panel(p->N, a, q.grid, q.mode, stream);
     if (st) return st;
   }
   return RKLT_OK;
@@ -979,7 +1043,7 @@ rklt_status rklt_plan_launches(const rklt_plan* p, int32_t* launches, int32_t* i
   if (!p) return fail(RKLT_E_INVAL, "rklt_plan_launches: plan is NULL");
   if (launches) *launches = p->nparts;
   if (images_per_class) {
-    images_per_class[0] = images_per_class[1] = images_per_class[2] = 0;
+    for (int c = 0; c < kClasses; ++c) images_per_class[c] = 0;
     for (int k = 0; k < p->nparts; ++k) images_per_class[p->parts[k].cls] += p->parts[k].n;
   }
   return RKLT_OK;

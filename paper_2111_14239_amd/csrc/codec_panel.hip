@@ -3,7 +3,9 @@
 // matrix-core and register kernels do not take.  The computation is the
 // separable one, B = T (A - ell) T^T in exact integers, B_hat = (s s^T) (.) B
 // on the first r zig-zag positions, A' = T_hat^-1 B_hat T_hat^-T + ell in
-// FP32, pixel = clip(floor(A' + 1/2)).
+// FP32, pixel = clip(floor(A' + 1/2)).  The same kernel codes with the
+// paper's float comparison transforms (exact KLT, DCT; §4.1 and Table 3):
+// B = M (A - ell) M^T in FP32, no scaling, A' = M^-1 B M^-T + ell.
 //
 // A wave codes one panel at a time: the PB blocks of one block row that
 // cover 128 pixel columns (64 for N = 32), i.e. 64 RPL (block, row) pairs,
@@ -108,9 +110,11 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// BIGT: entries of T beyond int8 (int32 row products instead of v_dot4).
-template <int N, bool PLAN, bool BIGT>
+// MODE (PanelMode): integer T within int8 (v_dot4), integer T beyond int8
+// (int32 row products), or a float transform (FP32 forward from Mf).
+template <int N, bool PLAN, int MODE>
 __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
+  constexpr bool BIGT = MODE == kPanelBigT, FLT = MODE == kPanelFloat;
   using P = Panel<N>;
   constexpr int NN = P::NN, PB = P::PB, RPL = P::RPL, W4 = P::W4, SP = P::SP;
   // per-lane table reads go through LDS; wave-uniform ones (rows of T and
@@ -197,22 +201,36 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
 #pragma unroll
       for (int k = 0; k < RPL; ++k) {
         const int p = lane + 64 * k;
-        uint32_t xs[W4];
+        if constexpr (FLT) {
+          // pixel - ell exactly in FP32, then y_j = sum_n M[j][n] x_n
+          float xf[N];
 #pragma unroll
-        for (int w = 0; w < W4; ++w) xs[w] = px[k][w] ^ 0x80808080u;
-        for (int j = 0; j < Dc; ++j) {
-          int y = lift * tf->sig[j];
-          if (!BIGT) {
+          for (int n = 0; n < N; ++n)
+            xf[n] = static_cast<float>((px[k][n / 4] >> (8 * (n % 4))) & 0xffu) - static_cast<float>(ell);
+          for (int j = 0; j < Dc; ++j) {
+            float y = 0.0f;
 #pragma unroll
-            for (int w = 0; w < W4; ++w) y = __builtin_amdgcn_sdot4(static_cast<int>(xs[w]), tf->Tw[j * W4 + w], y, false);
-          } else {
-#pragma unroll
-            for (int n = 0; n < N; ++n) {
-              const int x = __builtin_amdgcn_sbfe(static_cast<int>(xs[n / 4]), 8 * (n % 4), 8);
-              y = x * __builtin_amdgcn_sbfe(tf->T[j * N + n], 0, 24) + y;
-            }
+            for (int n = 0; n < N; ++n) y = fmaf(tf->Mf[j * N + n], xf[n], y);
+            buf[p * SP + j] = y;
           }
-          buf[p * SP + j] = __builtin_bit_cast(float, y);
+        } else {
+          uint32_t xs[W4];
+#pragma unroll
+          for (int w = 0; w < W4; ++w) xs[w] = px[k][w] ^ 0x80808080u;
+          for (int j = 0; j < Dc; ++j) {
+            int y = lift * tf->sig[j];
+            if (!BIGT) {
+#pragma unroll
+              for (int w = 0; w < W4; ++w) y = __builtin_amdgcn_sdot4(static_cast<int>(xs[w]), tf->Tw[j * W4 + w], y, false);
+            } else {
+#pragma unroll
+              for (int n = 0; n < N; ++n) {
+                const int x = __builtin_amdgcn_sbfe(static_cast<int>(xs[n / 4]), 8 * (n % 4), 8);
+                y = x * __builtin_amdgcn_sbfe(tf->T[j * N + n], 0, 24) + y;
+              }
+            }
+            buf[p * SP + j] = __builtin_bit_cast(float, y);
+          }
         }
       }
       wave_lds_sync();
@@ -221,9 +239,15 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
       for (int k = 0; k < RPL; ++k) {
         const int q = lane + 64 * k, b = q / N, j = q % N;
         if (j < Dc) {
+          // column j of the row sums: int24 (integer T) or FP32 (float transform)
           int Yc[N];
+          float Yf[N];
 #pragma unroll
-          for (int m = 0; m < N; ++m) Yc[m] = __builtin_amdgcn_sbfe(__builtin_bit_cast(int, buf[(m * PB + b) * SP + j]), 0, 24);
+          for (int m = 0; m < N; ++m) {
+            const float v = buf[(m * PB + b) * SP + j];
+            Yf[m] = v;
+            Yc[m] = __builtin_amdgcn_sbfe(__builtin_bit_cast(int, v), 0, 24);
+          }
           float Wc[N];
 #pragma unroll
           for (int m = 0; m < N; ++m) Wc[m] = 0.0f;
@@ -231,13 +255,23 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
           const bool vb = bx0 + b < bw;
           const int gb = by * bw + bx0 + b;  // block index in the image (dump layout)
           for (int i = 0; i < iend; ++i) {
-            int B = 0;
+            float bs;
+            if constexpr (FLT) {
+              // B_ij = sum_m M[i][m] Y[m][j]; no scaling
+              float B = 0.0f;
 #pragma unroll
-            for (int m = 0; m < N; ++m) B = __builtin_amdgcn_sbfe(tf->T[i * N + m], 0, 24) * Yc[m] + B;
-            const float bs = static_cast<float>(B) * sW[i * N + j];
-            if (a.dump && vb) {
-              if (im->coef) im->coef[static_cast<size_t>(gb) * NN + i * N + j] = B;
-              if (im->scaled) im->scaled[static_cast<size_t>(gb) * NN + i * N + j] = bs;
+              for (int m = 0; m < N; ++m) B = fmaf(tf->Mf[i * N + m], Yf[m], B);
+              bs = B;
+              if (a.dump && vb && im->scaled) im->scaled[static_cast<size_t>(gb) * NN + i * N + j] = bs;
+            } else {
+              int B = 0;
+#pragma unroll
+              for (int m = 0; m < N; ++m) B = __builtin_amdgcn_sbfe(tf->T[i * N + m], 0, 24) * Yc[m] + B;
+              bs = static_cast<float>(B) * sW[i * N + j];
+              if (a.dump && vb) {
+                if (im->coef) im->coef[static_cast<size_t>(gb) * NN + i * N + j] = B;
+                if (im->scaled) im->scaled[static_cast<size_t>(gb) * NN + i * N + j] = bs;
+              }
             }
             if (srank[i * N + j] < r) {
 #pragma unroll
@@ -292,15 +326,17 @@ rklt_status launched_panel() {
   return RKLT_OK;
 }
 
+template <int N, int MODE>
+void launch_panel_m(const KArgs& a, int grid, hipStream_t st) {
+  if (a.imgs) hipLaunchKernelGGL((rklt_panel_kernel<N, true, MODE>), dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL((rklt_panel_kernel<N, false, MODE>), dim3(grid), dim3(256), 0, st, a);
+}
+
 template <int N>
-void launch_panel_n(const KArgs& a, int grid, bool bigt, hipStream_t st) {
-  if (a.imgs) {
-    if (bigt) hipLaunchKernelGGL((rklt_panel_kernel<N, true, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((rklt_panel_kernel<N, true, false>), dim3(grid), dim3(256), 0, st, a);
-  } else {
-    if (bigt) hipLaunchKernelGGL((rklt_panel_kernel<N, false, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((rklt_panel_kernel<N, false, false>), dim3(grid), dim3(256), 0, st, a);
-  }
+void launch_panel_n(const KArgs& a, int grid, int mode, hipStream_t st) {
+  if (mode == kPanelFloat) launch_panel_m<N, kPanelFloat>(a, grid, st);
+  else if (mode == kPanelBigT) launch_panel_m<N, kPanelBigT>(a, grid, st);
+  else launch_panel_m<N, kPanelInt8>(a, grid, st);
 }
 
 }  // namespace
@@ -315,13 +351,13 @@ int panel_blocks(int N) {
   }
 }
 
-rklt_status launch_panel(int N, const KArgs& a, int grid, bool bigt, void* stream) {
+rklt_status launch_panel(int N, const KArgs& a, int grid, int mode, void* stream) {
   const hipStream_t st = static_cast<hipStream_t>(stream);
   switch (N) {
-    case 4: launch_panel_n<4>(a, grid, bigt, st); break;
-    case 8: launch_panel_n<8>(a, grid, bigt, st); break;
-    case 16: launch_panel_n<16>(a, grid, bigt, st); break;
-    case 32: launch_panel_n<32>(a, grid, bigt, st); break;
+    case 4: launch_panel_n<4>(a, grid, mode, st); break;
+    case 8: launch_panel_n<8>(a, grid, mode, st); break;
+    case 16: launch_panel_n<16>(a, grid, mode, st); break;
+    case 32: launch_panel_n<32>(a, grid, mode, st); break;
     default: return fail(RKLT_E_INVAL, "panel kernel: N=%d not supported", N);
   }
   return launched_panel();

@@ -15,6 +15,10 @@ void clear_error();
 
 rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out);
 rklt_status zigzag(int N, int32_t* order);
+rklt_status klt_matrix(int N, double rho, double* K);
+rklt_status dct_matrix(int N, double* C);
+// FP64 Gauss-Jordan inverse with partial pivoting; false if singular.
+bool invert_matrix(int n, const double* A, double* inv);
 // Exact inverse of an integer matrix with entries in [-8, 8], N <= 8:
 // T^-1 = adj / den in lowest terms, den > 0.  False if singular or out of range.
 bool exact_inverse(int N, const int32_t* T, int64_t* adj, int64_t* den);
@@ -62,13 +66,16 @@ struct alignas(256) DevTransform {
   //                        an exact inverse, else T^-1 (x) T^-1, in FP32
   int32_t m_ok, m_r1, m_path3, m_den;
   float m_inv, m_bias;
-  int32_t m_pad[2];
+  // float transforms (rklt_ctx_add_float_transform): is_float = 1, the
+  // forward matrix M in Mf, M^-1 transposed in Gt, w = 1; every integer
+  // field is zero and the kernels for integer transforms never see them
+  int32_t is_float, pad0;
   int32_t mF[2][2][64][4];
   _Float16 mV[2][8][64][8];
   float mVf[2][8][4][64];
   float w[RKLT_MAX_N * RKLT_MAX_N];     // s_i s_j at i*N + j
   float G[RKLT_MAX_N * RKLT_MAX_N];     // T_hat^-1 at m*N + i
-  float Ti[RKLT_MAX_N * RKLT_MAX_N];    // T^-1 = T_hat^-1 S at m*N + i
+  float Mf[RKLT_MAX_N * RKLT_MAX_N];    // float transforms: M at i*N + n
   int32_t T[RKLT_MAX_N * RKLT_MAX_N];   // T at i*N + j
   int32_t rank[RKLT_MAX_N * RKLT_MAX_N];  // zig-zag position of (i, j)
   // panel kernel (read as wave-uniform scalars): rows of T as int8x4 words
@@ -145,7 +152,10 @@ inline int diagonals_for(int N, int r) {
 rklt_status launch_block8(const KArgs& a, int grid, int wg, void* stream);
 rklt_status launch_mfma8(const KArgs& a, int grid, int wg, void* stream);
 int mfma8_resident_wgs_per_cu(int wg);
-rklt_status launch_panel(int N, const KArgs& a, int grid, bool bigt, void* stream);
+// Panel kernel arithmetic: integer T within int8 (v_dot4), integer T beyond
+// int8 (int32 products), or a float transform (FP32 throughout).
+enum PanelMode { kPanelInt8 = 0, kPanelBigT = 1, kPanelFloat = 2 };
+rklt_status launch_panel(int N, const KArgs& a, int grid, int mode, void* stream);
 
 // MSSIM of a plan's images (codec_quality.hip): one record per image in
 // slot order, tiles of 32 x 64 window positions numbered image by image.

@@ -57,9 +57,11 @@ double solve_bracketed(const FreqEq& eq, double lo, double hi) {
   return x;
 }
 
+}  // namespace
+
 // Gauss-Jordan inverse with partial pivoting, FP64.  Returns false when a
 // pivot is negligible against the row scale (singular matrix).
-bool invert(int n, const double* A, double* inv) {
+bool invert_matrix(int n, const double* A, double* inv) {
   double M[RKLT_MAX_N][2 * RKLT_MAX_N];
   double scale = 0.0;
   for (int i = 0; i < n; ++i) {
@@ -90,7 +92,43 @@ bool invert(int n, const double* A, double* inv) {
   return true;
 }
 
-}  // namespace
+rklt_status klt_matrix(int N, double rho, double* K) {
+  if (!K) return fail(RKLT_E_INVAL, "rklt_klt_matrix: K is NULL");
+  if (N < 2 || N > RKLT_MAX_N) return fail(RKLT_E_INVAL, "rklt_klt_matrix: N=%d outside 2..%d", N, RKLT_MAX_N);
+  if (!(rho > 0.0 && rho < 1.0)) return fail(RKLT_E_INVAL, "rklt_klt_matrix: rho=%g outside (0, 1)", rho);
+  // §2.1: one frequency in each open interval (k pi / N, (k+1) pi / N).
+  // w = 0 and w = pi are trivial zeros of the cleared equation, so the two
+  // outer brackets start a little way inside.
+  const FreqEq eq{N, 1.0 + rho * rho, 1.0 - rho * rho, rho};
+  double omega[RKLT_MAX_N], lambda[RKLT_MAX_N];
+  const double step = M_PI / N;
+  for (int k = 0; k < N; ++k) {
+    double lo = k * step, hi = (k + 1) * step;
+    if (k == 0) lo += 1e-7 * step;
+    if (k == N - 1) hi -= 1e-7 * step;
+    omega[k] = solve_bracketed(eq, lo, hi);
+    lambda[k] = (1.0 - rho * rho) / (1.0 + rho * rho - 2.0 * rho * std::cos(omega[k]));
+  }
+  // §2.1: basis vector k sampled at n (row k of K), with the frequency and the
+  // phase indexed by the basis index k.
+  for (int k = 0; k < N; ++k) {
+    const double amp = std::sqrt(2.0 / (N + lambda[k]));
+    for (int n = 0; n < N; ++n) K[k * N + n] = amp * std::sin(omega[k] * (n - 0.5 * (N - 1)) + 0.5 * (k + 1) * M_PI);
+  }
+  return RKLT_OK;
+}
+
+rklt_status dct_matrix(int N, double* C) {
+  if (!C) return fail(RKLT_E_INVAL, "rklt_dct_matrix: C is NULL");
+  if (N < 2 || N > RKLT_MAX_N) return fail(RKLT_E_INVAL, "rklt_dct_matrix: N=%d outside 2..%d", N, RKLT_MAX_N);
+  // orthonormal DCT-II: row k is c_k cos(pi (2n + 1) k / (2N)), c_0 = sqrt(1/N),
+  // c_k = sqrt(2/N) otherwise
+  for (int k = 0; k < N; ++k) {
+    const double c = std::sqrt((k == 0 ? 1.0 : 2.0) / N);
+    for (int n = 0; n < N; ++n) C[k * N + n] = c * std::cos(M_PI * (2 * n + 1) * k / (2.0 * N));
+  }
+  return RKLT_OK;
+}
 
 rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out) {
   if (!out) return fail(RKLT_E_INVAL, "rklt_build_transform: out is NULL");
@@ -106,27 +144,8 @@ rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out
   out->rho = rho;
   out->alpha = alpha;
 
-  // §2.1: one frequency in each open interval (k pi / N, (k+1) pi / N).
-  // w = 0 and w = pi are trivial zeros of the cleared equation, so the two
-  // outer brackets start a little way inside.
-  const FreqEq eq{N, 1.0 + rho * rho, 1.0 - rho * rho, rho};
-  double omega[RKLT_MAX_N], lambda[RKLT_MAX_N];
-  const double step = M_PI / N;
-  for (int k = 0; k < N; ++k) {
-    double lo = k * step, hi = (k + 1) * step;
-    if (k == 0) lo += 1e-7 * step;
-    if (k == N - 1) hi -= 1e-7 * step;
-    omega[k] = solve_bracketed(eq, lo, hi);
-    lambda[k] = (1.0 - rho * rho) / (1.0 + rho * rho - 2.0 * rho * std::cos(omega[k]));
-  }
-
-  // §2.1: basis vector k sampled at n (row k of K), with the frequency and the
-  // phase indexed by the basis index k.
-  for (int k = 0; k < N; ++k) {
-    const double amp = std::sqrt(2.0 / (N + lambda[k]));
-    for (int n = 0; n < N; ++n)
-      out->K[k * N + n] = amp * std::sin(omega[k] * (n - 0.5 * (N - 1)) + 0.5 * (k + 1) * M_PI);
-  }
+  rklt_status st = klt_matrix(N, rho, out->K);
+  if (st) return st;
 
   // Eq. (2): T = round(alpha K), round(x) = floor(x + 1/2).
   int max_abs = 0, max_l1 = 0;
@@ -171,7 +190,7 @@ rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out
   double That[RKLT_MAX_N * RKLT_MAX_N];
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) That[i * N + j] = out->s[i] * out->T[i * N + j];
-  if (!invert(N, That, out->G))
+  if (!invert_matrix(N, That, out->G))
     return fail(RKLT_E_SINGULAR, "rklt_build_transform: round(alpha K) is singular (N=%d rho=%g alpha=%g)",
                 N, rho, alpha);
   return RKLT_OK;

@@ -90,12 +90,15 @@ def _load():
         "rklt_plan_destroy": (st, [vp]),
         "rklt_plan_info": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_copy_bytes": (st, [vp, vp, C.c_size_t, vp]),
-        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 3)]),
+        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 4)]),
         "rklt_plan_update": (st, [vp, C.POINTER(Image), C.c_int32, vp]),
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_ctx_mfma_form": (st, [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
         "rklt_plan_autotune": (st, [vp, vp, C.c_int32, vp, C.POINTER(Tuning)]),
         "rklt_plan_mssim": (st, [vp, vp, vp]),
+        "rklt_klt_matrix": (st, [C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+        "rklt_dct_matrix": (st, [C.c_int32, C.POINTER(C.c_double)]),
+        "rklt_ctx_add_float_transform": (st, [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -109,7 +112,8 @@ EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_
             "rklt_ctx_destroy", "rklt_ctx_add_transform", "rklt_codec", "rklt_plan_create",
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
             "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form",
-            "rklt_plan_autotune", "rklt_plan_mssim")
+            "rklt_plan_autotune", "rklt_plan_mssim", "rklt_klt_matrix", "rklt_dct_matrix",
+            "rklt_ctx_add_float_transform")
 
 
 def lib():
@@ -163,6 +167,20 @@ def build_transform(N: int, rho: float, alpha: float) -> TransformInfo:
         s=np.ctypeslib.as_array(t.s)[:N].copy(),
         G=np.ctypeslib.as_array(t.G)[:n2].reshape(N, N).copy(),
         flags=t.flags, max_abs=t.max_abs, max_row_l1=t.max_row_l1, raw=t)
+
+
+def klt_matrix(N: int, rho: float) -> np.ndarray:
+    """rklt_klt_matrix: the exact KLT K_rho (rows the basis vectors), FP64."""
+    buf = (C.c_double * (N * N))()
+    _check(_lib.rklt_klt_matrix(int(N), float(rho), buf))
+    return np.ctypeslib.as_array(buf).reshape(N, N).copy()
+
+
+def dct_matrix(N: int) -> np.ndarray:
+    """rklt_dct_matrix: the orthonormal DCT-II (rows the basis vectors), FP64."""
+    buf = (C.c_double * (N * N))()
+    _check(_lib.rklt_dct_matrix(int(N), buf))
+    return np.ctypeslib.as_array(buf).reshape(N, N).copy()
 
 
 def zigzag(N: int) -> np.ndarray:
@@ -278,6 +296,33 @@ class Context:
             self._ids[key] = self.add_transform(build_transform(N, rho, alpha))
         return self._ids[key]
 
+    def add_float_transform(self, M) -> int:
+        """rklt_ctx_add_float_transform: upload an N x N float transform
+        (rows the basis vectors); returns its id."""
+        M = np.ascontiguousarray(M, dtype=np.float64)
+        if M.ndim != 2 or M.shape[0] != M.shape[1]:
+            raise ValueError("add_float_transform: M must be square")
+        i = C.c_int32()
+        _check(_lib.rklt_ctx_add_float_transform(self._h, int(M.shape[0]),
+                                                 M.ctypes.data_as(C.POINTER(C.c_double)), C.byref(i)))
+        return int(i.value)
+
+    def float_transform_id(self, kind: str, N: int = 8, rho: float | None = None) -> int:
+        """Id of a comparison transform, uploaded on first use: kind "dct"
+        (orthonormal DCT-II) or "klt" (exact KLT of correlation rho)."""
+        key = (kind, int(N), None if rho is None else float(rho))
+        if key not in self._ids:
+            if kind == "dct":
+                M = dct_matrix(N)
+            elif kind == "klt":
+                if rho is None:
+                    raise ValueError("float_transform_id: kind 'klt' needs rho")
+                M = klt_matrix(N, rho)
+            else:
+                raise ValueError(f"float_transform_id: unknown kind {kind!r}")
+            self._ids[key] = self.add_float_transform(M)
+        return self._ids[key]
+
     def transform_exact(self, tid: int) -> tuple[bool, int]:
         """(exact, den): whether the N = 8 register kernel reconstructs exactly."""
         e, d = C.c_int32(), C.c_int64()
@@ -319,10 +364,11 @@ class Plan:
         tiles, grid, pixels = C.c_int64(), C.c_int32(), C.c_int64()
         _check(_lib.rklt_plan_info(h, C.byref(tiles), C.byref(grid), C.byref(pixels)))
         self.tiles, self.grid, self.pixels = int(tiles.value), int(grid.value), int(pixels.value)
-        nl, per = C.c_int32(), (C.c_int32 * 3)()
+        nl, per = C.c_int32(), (C.c_int32 * 4)()
         _check(_lib.rklt_plan_launches(h, C.byref(nl), per))
         self.launches = int(nl.value)
-        self.images_per_class = [int(v) for v in per]  # [generic, register N=8, matrix-core N=8]
+        # [panel, register N=8, matrix-core N=8, panel with a float transform]
+        self.images_per_class = [int(v) for v in per]
         self.block8_images = self.images_per_class[1] + self.images_per_class[2]
 
     def run(self, res_ptr: int, stream=None):

@@ -133,6 +133,29 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert L.rklt_plan_mssim(None, None, None) == rklt.E_INVAL
     f = C.c_int32()
     assert L.rklt_ctx_mfma_form(None, 0, 1, C.byref(f)) == rklt.E_INVAL
+    assert L.rklt_klt_matrix(8, 0.5, None) == rklt.E_INVAL
+    assert L.rklt_dct_matrix(8, None) == rklt.E_INVAL
+    M = (C.c_double * 64)()
+    assert L.rklt_ctx_add_float_transform(None, 8, M, C.byref(f)) == rklt.E_INVAL
+
+
+def test_comparison_transforms_match_oracle():
+    # the float arms of the experiment: exact KLT (§2.1) and the orthonormal
+    # DCT-II, from the library's own host code, against the oracle's
+    from oracle import metrics as m
+    for N in (2, 4, 8, 16, 32):
+        assert np.allclose(rklt.dct_matrix(N), m.dct_matrix(N), atol=1e-15, rtol=0)
+        for rho in (0.05, 0.3, 0.4, 0.7, 0.8, 0.95):
+            assert np.allclose(rklt.klt_matrix(N, rho), o.klt(N, rho), atol=1e-12, rtol=0), (N, rho)
+            # the same K that rklt_build_transform reports
+            assert np.array_equal(rklt.klt_matrix(N, rho), rklt.build_transform(N, rho, 4.0).K)
+    for bad in ((1, 0.5), (33, 0.5), (8, 0.0), (8, 1.0), (8, math.nan)):
+        with pytest.raises(rklt.RkltError) as e:
+            rklt.klt_matrix(*bad)
+        assert e.value.status == rklt.E_INVAL
+    for N in (1, 33):
+        with pytest.raises(rklt.RkltError):
+            rklt.dct_matrix(N)
 
 
 def test_library_uses_torchs_hip_runtime():
