@@ -285,9 +285,11 @@ def block_sizes(ctx, steps: int) -> dict:
 def comparison_arms(ctx, src, dst, steps: int) -> dict:
     """The paper's float comparison transforms (the DCT and the exact KLT
     K_0.8; §4.1, Table 3) and, for reference, the rounded KLT (rho 0.9,
-    alpha 2), all at r = 15 (its figure setting) on the bench batch: one plan
-    each, timed like the main plan.  The float arms run on the panel kernel
-    in FP32; HBM fraction from 2 algorithmic bytes per pixel."""
+    alpha 2), all at r = 15 (its figure setting), and the rounded KLT with
+    the Appendix A quantiser (steps 4 + 2 (i + j), every coefficient kept),
+    on the bench batch: one plan each, timed like the main plan.  The float
+    and quantised arms run on the panel kernel; HBM fraction from 2
+    algorithmic bytes per pixel."""
     import torch
 
     from paper_2111_14239_amd import rklt
@@ -297,16 +299,21 @@ def comparison_arms(ctx, src, dst, steps: int) -> dict:
     res = rklt.new_results(n)
     stream = torch.cuda.current_stream()
     out = {}
-    arms = (("dct", ctx.float_transform_id("dct", 8)), ("klt_rho0.8", ctx.float_transform_id("klt", 8, 0.8)),
-            ("rklt_rho0.9_alpha2", ctx.transform_id(8, 0.9, 2.0)))
-    for name, tid in arms:
-        plan = ctx.plan([rklt.image_desc(src[i], tid, 15, dst=dst[i]) for i in range(n)])
+    i8 = np.arange(8)
+    Q = 4.0 + 2.0 * (i8[:, None] + i8[None, :])  # a frequency ramp of quantiser steps
+    arms = (("dct", ctx.float_transform_id("dct", 8), 15),
+            ("klt_rho0.8", ctx.float_transform_id("klt", 8, 0.8), 15),
+            ("rklt_rho0.9_alpha2", ctx.transform_id(8, 0.9, 2.0), 15),
+            ("rklt_rho0.9_alpha2_quantised_Q4+2(i+j)_r64", ctx.add_quantizer(ctx.transform_id(8, 0.9, 2.0), Q), 64))
+    for name, tid, r in arms:
+        plan = ctx.plan([rklt.image_desc(src[i], tid, r, dst=dst[i]) for i in range(n)])
         ms = _time_plan(plan, res, stream, steps)
         psnr = [r["psnr_db"] for r in rklt.read_results(res)]
         out[name] = {"ms_per_launch": ms, "value": pixels / (ms / 1e3) / 1e6, "unit": "Mpixel/s",
                      "hbm_frac": BYTES_PER_PIXEL * pixels / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                      "kernel_class": ("panel_float" if plan.images_per_class[3] else
-                                      "matrix_core_n8" if plan.images_per_class[2] else "other"),
+                                      "matrix_core_n8" if plan.images_per_class[2] else
+                                      "panel" if plan.images_per_class[0] else "other"),
                      "mean_psnr_db": float(np.mean(psnr))}
         plan.close()
     return out

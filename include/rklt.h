@@ -179,6 +179,25 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
  * E_HIP. */
 rklt_status rklt_ctx_add_float_transform(rklt_ctx* ctx, int32_t N, const double* M, int32_t* id_out);
 
+/* JPEG-style quantisation with the scaling matrix folded into the
+ * quantiser (Appendix A): returns a new id naming rounded transform
+ * `transform_id` together with the quantisation matrix Q (N x N, FP64,
+ * row-major, entries in (0, 1e6]).  Images coded with that id keep the first
+ * r zig-zag coefficients as usual (r = N*N keeps all) and replace their
+ * scaling by the quantiser:
+ *   code    c_ij = floor(t + 1/2),  t = fl32(B_ij * q_ij),
+ *           q_ij = fl32(s_i s_j / Q_ij) (computed in FP64 on the host): the
+ *           reciprocal of Q~ = Q / (s s^T), so B / Q~ = (T_hat A T_hat^T) / Q;
+ *   dequantised scaled coefficient Q_ij c_ij (FP32), then the usual inverse
+ *   A' = T_hat^-1 (Q (.) c) T_hat^-T + ell in FP32 and pixel rounding.
+ * The codes are exact functions of the integer B (the same FP32 steps on any
+ * IEEE machine).  These images run on the panel kernel (any N, any ell);
+ * scaled_out receives Q_ij c_ij for every coefficient (the quantiser's
+ * output before the zonal mask), coef_out the integer B.  An identical (T, Q) returns the existing id.  Errors: E_INVAL
+ * (NULL argument, unknown id, a float or already quantised transform, an
+ * entry of Q outside (0, 1e6] or NaN), E_NOMEM (table full), E_HIP. */
+rklt_status rklt_ctx_add_quantizer(rklt_ctx* ctx, int32_t transform_id, const double* Q, int32_t* id_out);
+
 /* Whether the N = 8 register kernel reconstructs transform `id` exactly:
  * T^-1 = adj / den with integer adj small enough that every step of the
  * inverse is exact, so reconstructed pixels equal floor(x + 1/2) of the exact
@@ -265,7 +284,7 @@ rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_
  *   class 1  the N = 8 register kernel: level shift 128, |T_ij| <= 127,
  *            128 * max row L1 <= 32767 (also every plan that dumps coefficients);
  *   class 0  the panel kernel (any N, any level shift): every other rounded
- *            transform;
+ *            transform, and every quantised one;
  *   class 3  the panel kernel in FP32: float transforms.
  * Reports the number of launches per run and, in images_per_class[4] (may be
  * NULL), how many images each class codes. */

@@ -86,7 +86,7 @@ bool block8_fits(const DevTransform& t, int ell) {
 
 int kernel_class(const DevTransform& t, int ell, bool dump) {
   if (t.is_float) return 3;
-  if (!block8_fits(t, ell)) return 0;
+  if (t.quant || !block8_fits(t, ell)) return 0;
   return (t.m_ok && !dump) ? 2 : 1;
 }
 
@@ -505,7 +505,7 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
   std::lock_guard<std::mutex> lock(ctx->mu);
   for (size_t k = 0; k < ctx->host.size(); ++k) {
     const DevTransform& o = ctx->host[k];
-    if (!o.is_float && o.N == N && std::memcmp(o.T, dt.T, sizeof(int32_t) * N * N) == 0) {
+    if (!o.is_float && !o.quant && o.N == N && std::memcmp(o.T, dt.T, sizeof(int32_t) * N * N) == 0) {
       *id_out = static_cast<int32_t>(k);
       return RKLT_OK;
     }
@@ -572,6 +572,59 @@ rklt_status rklt_ctx_add_float_transform(rklt_ctx* ctx, int32_t N, const double*
   if (e != hipSuccess) return hip_fail("hipSetDevice", e);
   e = hipMemcpy(ctx->d_table + id, &dt, sizeof(dt), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail("rklt_ctx_add_float_transform: hipMemcpy", e);
+  ctx->host.push_back(dt);
+  *id_out = id;
+  return RKLT_OK;
+}
+
+rklt_status rklt_ctx_add_quantizer(rklt_ctx* ctx, int32_t transform_id, const double* Q, int32_t* id_out) {
+  clear_error();
+  if (!ctx || !Q || !id_out) return fail(RKLT_E_INVAL, "rklt_ctx_add_quantizer: NULL argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (transform_id < 0 || transform_id >= static_cast<int>(ctx->host.size()))
+    return fail(RKLT_E_INVAL, "rklt_ctx_add_quantizer: unknown transform id %d", transform_id);
+  DevTransform dt = ctx->host[transform_id];
+  if (dt.is_float || dt.quant)
+    return fail(RKLT_E_INVAL, "rklt_ctx_add_quantizer: transform %d is not a rounded (integer) transform",
+                transform_id);
+  const int N = dt.N;
+  for (int k = 0; k < N * N; ++k)
+    if (!(Q[k] > 0.0) || !(Q[k] <= 1e6))
+      return fail(RKLT_E_INVAL, "rklt_ctx_add_quantizer: Q[%d]=%g outside (0, 1e6]", k, Q[k]);
+  // s_i s_j = w_ij exactly as the host designed it: recompute s in FP64
+  double s[RKLT_MAX_N];
+  for (int i = 0; i < N; ++i) {
+    int64_t d = 0;
+    for (int j = 0; j < N; ++j) d += static_cast<int64_t>(dt.T[i * N + j]) * dt.T[i * N + j];
+    s[i] = 1.0 / std::sqrt(static_cast<double>(d));
+  }
+  // quantised entries run on the panel kernel only: neither N = 8 kernel
+  // (nor its exactness report) applies
+  dt.quant = 1;
+  dt.m_ok = 0;
+  dt.exact = 0;
+  dt.den = 0;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      dt.qinv[i * N + j] = static_cast<float>((s[i] * s[j]) / Q[i * N + j]);
+      dt.qstep[i * N + j] = static_cast<float>(Q[i * N + j]);
+    }
+  for (size_t k = 0; k < ctx->host.size(); ++k) {
+    const DevTransform& o = ctx->host[k];
+    if (o.quant && o.N == N && std::memcmp(o.T, dt.T, sizeof(int32_t) * N * N) == 0 &&
+        std::memcmp(o.qinv, dt.qinv, sizeof(float) * N * N) == 0 &&
+        std::memcmp(o.qstep, dt.qstep, sizeof(float) * N * N) == 0) {
+      *id_out = static_cast<int32_t>(k);
+      return RKLT_OK;
+    }
+  }
+  if (ctx->host.size() >= static_cast<size_t>(kMaxTransforms))
+    return fail(RKLT_E_NOMEM, "rklt_ctx_add_quantizer: table full (%d transforms)", kMaxTransforms);
+  const int id = static_cast<int>(ctx->host.size());
+  hipError_t e = use_device(ctx->device);
+  if (e != hipSuccess) return hip_fail("hipSetDevice", e);
+  e = hipMemcpy(ctx->d_table + id, &dt, sizeof(dt), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail("rklt_ctx_add_quantizer: hipMemcpy", e);
   ctx->host.push_back(dt);
   *id_out = id;
   return RKLT_OK;

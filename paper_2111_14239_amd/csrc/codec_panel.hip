@@ -5,7 +5,9 @@
 // on the first r zig-zag positions, A' = T_hat^-1 B_hat T_hat^-T + ell in
 // FP32, pixel = clip(floor(A' + 1/2)).  The same kernel codes with the
 // paper's float comparison transforms (exact KLT, DCT; §4.1 and Table 3):
-// B = M (A - ell) M^T in FP32, no scaling, A' = M^-1 B M^-T + ell.
+// B = M (A - ell) M^T in FP32, no scaling, A' = M^-1 B M^-T + ell.  A
+// quantised transform entry (Appendix A) replaces the scaling of each kept
+// coefficient by the quantiser: code round(B / Q~), dequantised Q * code.
 //
 // A wave codes one panel at a time: the PB blocks of one block row that
 // cover 128 pixel columns (64 for N = 32), i.e. 64 RPL (block, row) pairs,
@@ -110,6 +112,19 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Appendix A quantiser: code c = round(B / Q~), Q~ = Q / (s s^T), with
+// t = fl32(B * fl32(1 / Q~)) and round = floor(t + 1/2), evaluated exactly as
+// floor(t) + [t - floor(t) >= 1/2]; returns the dequantised coefficient of
+// T_hat A T_hat^T, Q c.  Contraction is off so that t is rounded once and
+// the decision is taken on that FP32 value, not on an FMA's exact product.
+__device__ __forceinline__ float quantise(int B, float qinv, float qstep) {
+#pragma clang fp contract(off)
+  const float t = static_cast<float>(B) * qinv;
+  const float f = floorf(t);
+  const float c = f + (t - f >= 0.5f ? 1.0f : 0.0f);
+  return c * qstep;
+}
+
 // MODE (PanelMode): integer T within int8 (v_dot4), integer T beyond int8
 // (int32 row products), or a float transform (FP32 forward from Mf).
 template <int N, bool PLAN, int MODE>
@@ -120,6 +135,7 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
   // per-lane table reads go through LDS; wave-uniform ones (rows of T and
   // T_hat^-1) are scalar loads from the transform table
   __shared__ float sW[NN];           // s_i s_j
+  __shared__ float sQi[NN], sQs[NN];  // quantiser: 1 / Q~ and Q (quantised entries only)
   __shared__ int16_t srank[NN];      // zig-zag rank of (i, j)
   // per wave: row sums Y[b][m][j], then W (in place), at ((m PB + b) SP + j)
   __shared__ float sbuf[4][P::BUF];
@@ -138,6 +154,8 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
       __syncthreads();
       for (int k = threadIdx.x; k < NN; k += blockDim.x) {
         sW[k] = tf->w[k];
+        sQi[k] = tf->qinv[k];
+        sQs[k] = tf->qstep[k];
         srank[k] = static_cast<int16_t>(tf->rank[k]);
       }
       __syncthreads();
@@ -145,6 +163,7 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
     }
     const int r = __builtin_amdgcn_readfirstlane(im->r);
     const int ell = __builtin_amdgcn_readfirstlane(im->ell);
+    const bool quant = !FLT && tf->quant != 0;
     const int D = a.dump ? 2 * N - 1 : __builtin_amdgcn_readfirstlane(im->D);
     const int Dc = D < N ? D : N;  // columns j that hold a needed coefficient
     const int bw = __builtin_amdgcn_readfirstlane(im->bw), bwp = __builtin_amdgcn_readfirstlane(im->bwp);
@@ -267,7 +286,11 @@ __global__ __launch_bounds__(256) void rklt_panel_kernel(KArgs a) {
               int B = 0;
 #pragma unroll
               for (int m = 0; m < N; ++m) B = __builtin_amdgcn_sbfe(tf->T[i * N + m], 0, 24) * Yc[m] + B;
-              bs = static_cast<float>(B) * sW[i * N + j];
+              if (quant) {
+                bs = quantise(B, sQi[i * N + j], sQs[i * N + j]);
+              } else {
+                bs = static_cast<float>(B) * sW[i * N + j];
+              }
               if (a.dump && vb) {
                 if (im->coef) im->coef[static_cast<size_t>(gb) * NN + i * N + j] = B;
                 if (im->scaled) im->scaled[static_cast<size_t>(gb) * NN + i * N + j] = bs;

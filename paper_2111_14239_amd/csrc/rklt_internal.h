@@ -68,8 +68,10 @@ struct alignas(256) DevTransform {
   float m_inv, m_bias;
   // float transforms (rklt_ctx_add_float_transform): is_float = 1, the
   // forward matrix M in Mf, M^-1 transposed in Gt, w = 1; every integer
-  // field is zero and the kernels for integer transforms never see them
-  int32_t is_float, pad0;
+  // field is zero and the kernels for integer transforms never see them.
+  // Quantised entries (rklt_ctx_add_quantizer): quant = 1, a copy of an
+  // integer transform plus qinv and qstep below
+  int32_t is_float, quant;
   int32_t mF[2][2][64][4];
   _Float16 mV[2][8][64][8];
   float mVf[2][8][4][64];
@@ -83,6 +85,10 @@ struct alignas(256) DevTransform {
   // |T| > 127) and T_hat^-1 transposed (Gt[i * N + m] = G[m * N + i])
   int32_t Tw[RKLT_MAX_N * RKLT_MAX_N / 4];
   float Gt[RKLT_MAX_N * RKLT_MAX_N];
+  // quantiser (quant = 1): qinv = fl32(s_i s_j / Q_ij), the reciprocal of
+  // Q~ = Q / (s s^T); qstep = fl32(Q_ij); at i*N + j
+  float qinv[RKLT_MAX_N * RKLT_MAX_N];
+  float qstep[RKLT_MAX_N * RKLT_MAX_N];
 };
 
 // One image of a launch (device memory for a plan, a kernel argument for the

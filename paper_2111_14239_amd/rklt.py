@@ -99,6 +99,7 @@ def _load():
         "rklt_klt_matrix": (st, [C.c_int32, C.c_double, C.POINTER(C.c_double)]),
         "rklt_dct_matrix": (st, [C.c_int32, C.POINTER(C.c_double)]),
         "rklt_ctx_add_float_transform": (st, [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "rklt_ctx_add_quantizer": (st, [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -113,7 +114,7 @@ EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
             "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form",
             "rklt_plan_autotune", "rklt_plan_mssim", "rklt_klt_matrix", "rklt_dct_matrix",
-            "rklt_ctx_add_float_transform")
+            "rklt_ctx_add_float_transform", "rklt_ctx_add_quantizer")
 
 
 def lib():
@@ -305,6 +306,15 @@ class Context:
         i = C.c_int32()
         _check(_lib.rklt_ctx_add_float_transform(self._h, int(M.shape[0]),
                                                  M.ctypes.data_as(C.POINTER(C.c_double)), C.byref(i)))
+        return int(i.value)
+
+    def add_quantizer(self, tid: int, Q) -> int:
+        """rklt_ctx_add_quantizer: id of rounded transform `tid` with the
+        N x N quantisation matrix Q (Appendix A)."""
+        Q = np.ascontiguousarray(Q, dtype=np.float64)
+        i = C.c_int32()
+        _check(_lib.rklt_ctx_add_quantizer(self._h, int(tid), Q.ctypes.data_as(C.POINTER(C.c_double)),
+                                           C.byref(i)))
         return int(i.value)
 
     def float_transform_id(self, kind: str, N: int = 8, rho: float | None = None) -> int:

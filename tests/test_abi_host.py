@@ -137,6 +137,7 @@ def test_null_arguments_are_rejected_without_a_gpu():
     assert L.rklt_dct_matrix(8, None) == rklt.E_INVAL
     M = (C.c_double * 64)()
     assert L.rklt_ctx_add_float_transform(None, 8, M, C.byref(f)) == rklt.E_INVAL
+    assert L.rklt_ctx_add_quantizer(None, 0, M, C.byref(f)) == rklt.E_INVAL
 
 
 def test_comparison_transforms_match_oracle():
