@@ -149,6 +149,52 @@ rklt_status rklt_zigzag(int32_t N, int32_t* order);
 rklt_status rklt_klt_matrix(int32_t N, double rho, double* K);
 rklt_status rklt_dct_matrix(int32_t N, double* C);
 
+/* ---- host-side design tools (§3, §3.1; no GPU needed) ------------------- */
+
+/* Figures of merit of an N x N transform T_hat (FP64, row-major, rows the
+ * basis vectors), for the unit-variance first-order Markov model of
+ * correlation rho, R_ij = rho^|i-j|:
+ *   coding_gain_db     unified coding gain (§3.1.1), -(10/N) sum_k
+ *                      log10(A_k B_k), A_k = h_k R h_k^T (h_k row k of
+ *                      T_hat), B_k = squared norm of row k of T_hat^-1;
+ *   coding_gain_tt_db  the same with T_hat^T in place of T_hat^-1 (equal for
+ *                      an orthonormal T_hat; the reading under which the
+ *                      paper's Table 2 values of its non-orthogonal matrices
+ *                      are reproduced);
+ *   efficiency_pct     transform efficiency (§3.1.2), 100 sum_i |r_ii| /
+ *                      sum_ij |r_ij|, r = T_hat R T_hat^T;
+ *   mse                (1/N) tr(D R D^T), D = ref - T_hat (§3.1.3);
+ *   error_energy       pi ||D||_F^2 (§3.1.4).
+ * `ref` is the matrix T_hat is compared with (K_rho in Table 2, the DCT for
+ * the RDCT).  Errors: E_INVAL (NULL, N outside 2..32, rho outside (0, 1), a
+ * non-finite entry), E_SINGULAR (T_hat singular). */
+typedef struct {
+  double coding_gain_db;
+  double coding_gain_tt_db;
+  double efficiency_pct;
+  double mse;
+  double error_energy;
+} rklt_measures;
+rklt_status rklt_transform_measures(int32_t N, const double* That, const double* ref, double rho,
+                                    rklt_measures* out);
+
+/* Algorithm 1 (§3): sweep rho over step, 2 step, ... (the grid points below
+ * 1) and record every T' = round(alpha K_rho) (round(x) = floor(x + 1/2))
+ * that differs from the previous one, starting from the zero matrix.  Entry
+ * k holds the first and last grid rho that gave it and T' (N x N in the first
+ * N*N entries of T).  At most `cap` entries are written to `out`
+ * (caller-owned); *count receives the total, so a call with cap = 0 sizes
+ * the array.  Errors: E_INVAL (count NULL, out NULL with cap > 0, N outside
+ * 2..32, alpha not positive and finite, step outside (0, 1/2) or finer than
+ * 1e-6), E_RANGE (entries beyond 1e6). */
+typedef struct {
+  double rho_first;
+  double rho_last;
+  int32_t T[RKLT_MAX_N * RKLT_MAX_N];
+} rklt_design_entry;
+rklt_status rklt_algorithm1(int32_t N, double alpha, double step, rklt_design_entry* out, int32_t cap,
+                            int32_t* count);
+
 /* ---- device context ----------------------------------------------------- */
 
 /* Create a context on HIP device `device`.  The context owns a device-side

@@ -522,6 +522,18 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
   return RKLT_OK;
 }
 
+rklt_status rklt_transform_measures(int32_t N, const double* That, const double* ref, double rho,
+                                    rklt_measures* out) {
+  clear_error();
+  return transform_measures(N, That, ref, rho, out);
+}
+
+rklt_status rklt_algorithm1(int32_t N, double alpha, double step, rklt_design_entry* out, int32_t cap,
+                            int32_t* count) {
+  clear_error();
+  return algorithm1(N, alpha, step, out, cap, count);
+}
+
 rklt_status rklt_klt_matrix(int32_t N, double rho, double* K) {
   clear_error();
   return klt_matrix(N, rho, K);

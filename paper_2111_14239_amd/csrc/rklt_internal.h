@@ -17,6 +17,8 @@ rklt_status build_transform(int N, double rho, double alpha, rklt_transform* out
 rklt_status zigzag(int N, int32_t* order);
 rklt_status klt_matrix(int N, double rho, double* K);
 rklt_status dct_matrix(int N, double* C);
+rklt_status transform_measures(int N, const double* That, const double* ref, double rho, rklt_measures* out);
+rklt_status algorithm1(int N, double alpha, double step, rklt_design_entry* out, int cap, int* count);
 // FP64 Gauss-Jordan inverse with partial pivoting; false if singular.
 bool invert_matrix(int n, const double* A, double* inv);
 // Exact inverse of an integer matrix with entries in [-8, 8], N <= 8:

@@ -61,6 +61,15 @@ class Result(C.Structure):
 RESULT_BYTES = C.sizeof(Result)  # 32
 
 
+class Measures(C.Structure):
+    _fields_ = [("coding_gain_db", C.c_double), ("coding_gain_tt_db", C.c_double),
+                ("efficiency_pct", C.c_double), ("mse", C.c_double), ("error_energy", C.c_double)]
+
+
+class DesignEntry(C.Structure):
+    _fields_ = [("rho_first", C.c_double), ("rho_last", C.c_double), ("T", C.c_int32 * (MAX_N * MAX_N))]
+
+
 class Tuning(C.Structure):
     _fields_ = [("wg_threads", C.c_int32), ("blocks_per_thread", C.c_int32),
                 ("grid_wgs", C.c_int32), ("reserved", C.c_int32)]
@@ -100,6 +109,10 @@ def _load():
         "rklt_dct_matrix": (st, [C.c_int32, C.POINTER(C.c_double)]),
         "rklt_ctx_add_float_transform": (st, [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
         "rklt_ctx_add_quantizer": (st, [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+        "rklt_transform_measures": (st, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                                         C.POINTER(Measures)]),
+        "rklt_algorithm1": (st, [C.c_int32, C.c_double, C.c_double, C.POINTER(DesignEntry), C.c_int32,
+                                 C.POINTER(C.c_int32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -114,7 +127,8 @@ EXPORTED = ("rklt_last_error", "rklt_build_transform", "rklt_zigzag", "rklt_ctx_
             "rklt_plan_run", "rklt_plan_destroy", "rklt_plan_info", "rklt_copy_bytes",
             "rklt_plan_launches", "rklt_ctx_transform_exact", "rklt_plan_update", "rklt_ctx_mfma_form",
             "rklt_plan_autotune", "rklt_plan_mssim", "rklt_klt_matrix", "rklt_dct_matrix",
-            "rklt_ctx_add_float_transform", "rklt_ctx_add_quantizer")
+            "rklt_ctx_add_float_transform", "rklt_ctx_add_quantizer", "rklt_transform_measures",
+            "rklt_algorithm1")
 
 
 def lib():
@@ -182,6 +196,31 @@ def dct_matrix(N: int) -> np.ndarray:
     buf = (C.c_double * (N * N))()
     _check(_lib.rklt_dct_matrix(int(N), buf))
     return np.ctypeslib.as_array(buf).reshape(N, N).copy()
+
+
+def transform_measures(That, ref, rho: float) -> dict:
+    """rklt_transform_measures: Cg (two readings), eta, MSE and epsilon of
+    T_hat against `ref` for the Markov-1 model of correlation rho (§3.1)."""
+    That = np.ascontiguousarray(That, dtype=np.float64)
+    ref = np.ascontiguousarray(ref, dtype=np.float64)
+    if That.shape != ref.shape or That.ndim != 2 or That.shape[0] != That.shape[1]:
+        raise ValueError("transform_measures: two square matrices of one shape")
+    m = Measures()
+    P = C.POINTER(C.c_double)
+    _check(_lib.rklt_transform_measures(int(That.shape[0]), That.ctypes.data_as(P), ref.ctypes.data_as(P),
+                                        float(rho), C.byref(m)))
+    return {f: float(getattr(m, f)) for f, _ in Measures._fields_}
+
+
+def algorithm1(N: int, alpha: float, step: float) -> list[tuple[float, float, np.ndarray]]:
+    """rklt_algorithm1: the distinct round(alpha K_rho) over the rho grid
+    step, 2 step, ...: (first rho, last rho, T) per matrix."""
+    n = C.c_int32()
+    _check(_lib.rklt_algorithm1(int(N), float(alpha), float(step), None, 0, C.byref(n)))
+    arr = (DesignEntry * max(n.value, 1))()
+    _check(_lib.rklt_algorithm1(int(N), float(alpha), float(step), arr, n.value, C.byref(n)))
+    return [(e.rho_first, e.rho_last, np.ctypeslib.as_array(e.T)[:N * N].reshape(N, N).astype(np.int64))
+            for e in arr[:n.value]]
 
 
 def zigzag(N: int) -> np.ndarray:
