@@ -331,8 +331,11 @@ rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_
  *            128 * max row L1 <= 32767 (also every plan that dumps coefficients);
  *   class 0  the panel kernel (any N, any level shift): every other rounded
  *            transform, and every quantised one;
- *   class 3  the panel kernel in FP32: float transforms.
- * Reports the number of launches per run and, in images_per_class[4] (may be
+ *   class 3  the panel kernel in FP32: float transforms;
+ *   class 4  the N in {16, 32} matrix-core kernel: level shift 128,
+ *            |T_ij| <= 127 and 128 * max row L1 <= 32640 (every transform of
+ *            alpha = 8 / max|K| at those N), no coefficient dump.
+ * Reports the number of launches per run and, in images_per_class[5] (may be
  * NULL), how many images each class codes. */
 rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* images_per_class);
 

@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librklt.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["codec.hip", "codec_mfma.hip", "codec_panel.hip", "codec_quality.hip", "abi.cpp", "transform.cpp", "design.cpp"]
+SOURCES = ["codec.hip", "codec_mfma.hip", "codec_panel.hip", "codec_quality.hip", "codec_mfma32.hip", "abi.cpp", "transform.cpp", "design.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

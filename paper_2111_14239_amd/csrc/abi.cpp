@@ -38,8 +38,8 @@ struct PlanPart {
 
 // Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
 // 0 = panel kernel (integer T, any N, any level shift), 3 = panel kernel for
-// float transforms.
-constexpr int kClasses = 4;
+// float transforms, 4 = matrix-core kernel for N in {16, 32}.
+constexpr int kClasses = 5;
 
 struct rklt_plan {
   rklt_ctx* ctx = nullptr;
@@ -86,7 +86,9 @@ bool block8_fits(const DevTransform& t, int ell) {
 
 int kernel_class(const DevTransform& t, int ell, bool dump) {
   if (t.is_float) return 3;
-  if (t.quant || !block8_fits(t, ell)) return 0;
+  if (t.quant) return 0;
+  if (t.m32_ok && ell == 128 && !dump) return 4;
+  if (!block8_fits(t, ell)) return 0;
   return (t.m_ok && !dump) ? 2 : 1;
 }
 
@@ -502,6 +504,34 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
     }
   }
 
+  if ((N == 16 || N == 32) && max_abs <= 127 && 128 * max_l1 <= 32640) {
+    // N in {16, 32} matrix-core operands (layout in DevTransform): Tb and Gb
+    // on the block diagonal of a 32 x 32 region, K order kap(e, h)
+    auto kap = [](int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); };
+    dt.m32_ok = 1;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int h = lane >> 5, c = lane & 31;
+      for (int w = 0; w < 4; ++w) {
+        uint32_t word = 0;
+        for (int b = 0; b < 4; ++b) {
+          const int n = kap(4 * w + b, h);
+          const int v = (c / N == n / N) ? t->T[(c % N) * N + n % N] : 0;
+          word |= (static_cast<uint32_t>(v) & 0xffu) << (8 * b);
+        }
+        dt.m32T[lane][w] = static_cast<int32_t>(word);
+      }
+      for (int tt = 0; tt < 16; ++tt) {
+        const int j = kap(tt, h);
+        const bool diag = c / N == j / N;
+        dt.m32G[tt][lane] = diag ? static_cast<float>(t->G[(c % N) * N + j % N]) : 0.0f;
+        // coefficient (c, j) of the region is coefficient (c % N, j % N) of
+        // one of its blocks (all four quadrants hold coefficients)
+        dt.m32W[tt][lane] = static_cast<float>(t->s[c % N] * t->s[j % N]);
+        dt.m32R[tt][lane] = static_cast<int16_t>(dt.rank[(c % N) * N + j % N]);
+      }
+    }
+  }
+
   std::lock_guard<std::mutex> lock(ctx->mu);
   for (size_t k = 0; k < ctx->host.size(); ++k) {
     const DevTransform& o = ctx->host[k];
@@ -614,6 +644,7 @@ rklt_status rklt_ctx_add_quantizer(rklt_ctx* ctx, int32_t transform_id, const do
   // (nor its exactness report) applies
   dt.quant = 1;
   dt.m_ok = 0;
+  dt.m32_ok = 0;
   dt.exact = 0;
   dt.den = 0;
   for (int i = 0; i < N; ++i)
@@ -667,10 +698,12 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int PB = panel_blocks(N);
     if (cls == 2) mfma8_pad_rows(a.one);
     if (panel_class(cls)) panel_pad_rows(a.one, PB, N);
+    if (cls == 4) mfma32_regions(a.one);
     a.one.tile0 = 0;
     a.one.slot = 0;
     a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
                         : cls == 1 ? image_tile_blocks(a.one, wg * bpt, wg)
+                        : cls == 4 ? image_tile_blocks(a.one, 16, 4)
                                    : image_tile_blocks(a.one, 4 * PB, 4 * PB);
     a.one.ntiles = (a.one.nblocks + a.one.tile_blocks - 1) / a.one.tile_blocks;
     a.total_tiles = a.one.ntiles;
@@ -681,6 +714,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int grid = a.total_tiles;
     return cls == 2 ? launch_mfma8(a, grid, wg, stream)
            : cls == 1 ? launch_block8(a, grid, wg, stream)
+           : cls == 4 ? launch_mfma32(a, grid, stream)
                       : launch_panel(N, a, grid, mode, stream);
   }
 }
@@ -708,15 +742,17 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 // (the plan's host image of the device buffer).
 rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int N,
                        PlanPart* q, std::vector<unsigned char>& img) {
-  const bool b8 = !panel_class(cls);
-  // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds
+  const bool b8 = cls == 1 || cls == 2;
+  // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds;
+  // N in {16, 32} matrix-core kernel: tiles of 64 regions (16 per wave)
   const int PB = panel_blocks(N);
-  const int base = cls == 2 ? (wg / 2) * bpt : b8 ? wg * bpt : 64 * PB;
-  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : 4 * PB;
+  const int base = cls == 2 ? (wg / 2) * bpt : cls == 1 ? wg * bpt : cls == 4 ? 64 : 64 * PB;
+  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : cls == 4 ? 4 : 4 * PB;
   q->mode = cls == 3 ? kPanelFloat : kPanelInt8;
   int64_t total = 0;
   for (auto& d : imgs) {
-    if (!b8) {
+    if (cls == 4) mfma32_regions(d);
+    if (panel_class(cls)) {
       panel_pad_rows(d, PB, N);
       if (cls == 0 && ctx->host[d.tid].max_abs > 127) q->mode = kPanelBigT;
     }
@@ -826,7 +862,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   p->pixels = pixels;
   p->nparts = 0;
   p->h_image.clear();
-  for (int c : {2, 1, 3, 0}) {
+  for (int c : {2, 4, 1, 3, 0}) {
     if (by_class[c].empty()) continue;
     st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts], p->h_image);
     if (st) return st;
@@ -1057,6 +1093,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.dump = p->dump ? 1 : 0;
     const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
                            : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
+                           : q.cls == 4 ? launch_mfma32(a, q.grid, stream)
                                         : launch_panel(p->N, a, q.grid, q.mode, stream);
     if (st) return st;
   }

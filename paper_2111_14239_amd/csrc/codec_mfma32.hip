@@ -1,0 +1,199 @@
+// Matrix-core kernel of the codec for block lengths N in {16, 32} (§4.1,
+// Appendix A; level shift 128, |T_ij| <= 127 and 128 L1 < 32640 with L1 the
+// largest row sum of |T|).  A wave codes one 32 x 32 pixel region per step:
+// one N = 32 block, or 2 x 2 N = 16 blocks through the block-diagonal Tb
+// (T twice on the diagonal; the off-diagonal products are zero, so the
+// blocks stay independent).  Every stage is a 32 x 32 x 32 product:
+//   row stage      Y  = (A - 128) Tb^T           v_mfma_i32_32x32x32_i8
+//   column stage   B^T = Y^T Tb^T                two v_mfma_i32_32x32x32_i8
+//                  (Y = 256 hi + lo, hi and lo signed bytes: |Y| <= 128 L1)
+//   zonal + S      B_hat = (s_i s_j) B on the first r zig-zag positions, FP32
+//   inverse        Z = B_hat Gb^T, A'^T = Z^T Gb^T  v_mfma_f32_32x32x2_f32
+//                  (Gb = T_hat^-1 on the block diagonal)
+//   pixel          clip(floor(A' + 128 + 1/2)), squared error
+// so B = T (A - 128) T^T is exact int32 and the inverse is FP32.
+//
+// Layouts.  With h = lane / 32 and c = lane % 32, accumulator register t of
+// lane l holds row kap(t, h) = 8 (t / 4) + 4 h + t % 4, column c; an int8
+// operand lane holds row (A) or column (B) c and 16 K elements, an FP32
+// operand lane one K element (h).  The K order of a product only has to
+// agree between its two operands, so every stage reads the previous stage's
+// accumulator registers as they are: K element e of lane l is index
+// kap(e, h), and the tables m32T, m32G of the transform record hold Tb and
+// Gb in that order.  Lane l loads row c of the region at the pixel columns
+// kap(0..15, h) (four 32-bit words at columns 8q + 4h), and the last product
+// returns exactly those pixels of the reconstruction to it, so the store and
+// the squared error need no exchange.
+//
+// Truncation: a step t of the inverse products carries columns (then rows)
+// kap(t, 0) and kap(t, 1); when both are >= D modulo N (D anti-diagonals
+// hold every kept coefficient) all its coefficients are zero and the step is
+// skipped.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.h"
+#include "rklt_internal.h"
+
+namespace rklt {
+namespace {
+
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef int v16i32 __attribute__((ext_vector_type(16)));
+typedef float v16f32 __attribute__((ext_vector_type(16)));
+
+constexpr uint32_t kRegionOut = 0x80000000u;  // out-of-range buffer offset: zero load, dropped store
+constexpr int kRegionFlags = 0x00020000;
+
+__host__ __device__ constexpr int kap(int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); }
+
+// Pixel words of row c of region (ry, rx): columns 8q + 4h .. + 3.
+struct RegionRows {
+  uint32_t os[4], od[4];
+  bool ok[4];
+};
+
+__device__ __forceinline__ RegionRows region_rows(int g, int rw, int H, int W, int ps, int pd, int c, int h,
+                                                  bool in_tile) {
+  RegionRows rr;
+  const int ry = g / rw, rx = g - ry * rw;
+  const int row = ry * 32 + c;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = rx * 32 + 8 * q + 4 * h;
+    rr.ok[q] = in_tile && row < H && col < W;  // W is a multiple of 16: a word is all in or all out
+    rr.os[q] = rr.ok[q] ? static_cast<uint32_t>(row) * ps + col : kRegionOut;
+    rr.od[q] = rr.ok[q] ? static_cast<uint32_t>(row) * pd + col : kRegionOut;
+  }
+  return rr;
+}
+
+template <bool PLAN>
+__global__ __launch_bounds__(256) void rklt_mfma32_kernel(KArgs a) {
+  __shared__ unsigned long long red[4];
+  const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  int loaded = -1, loaded_r = -1;
+  v4i32 Tw = {0, 0, 0, 0};
+  float G[16], WM[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) G[t] = WM[t] = 0.0f;
+  const v16i32 zi = {};
+  const v16f32 zf = {};
+  const ConstInt tile_img = (ConstInt)(a.tile_img);
+  for (int tile = tile_begin(a.total_tiles); tile < tile_end_of(a.total_tiles); ++tile) {
+    const int ii = PLAN ? __builtin_amdgcn_readfirstlane(tile_img[tile]) : 0;
+    const ConstImage im = PLAN ? (ConstImage)(a.imgs + ii) : (ConstImage)(&a.one);
+    const int tid = __builtin_amdgcn_readfirstlane(im->tid);
+    const int r = __builtin_amdgcn_readfirstlane(im->r);
+    const DevTransform* tf = a.tf + tid;
+    if (tid != loaded || r != loaded_r) {
+      // per-lane operands of the transform; weights of ranks >= r zeroed
+      Tw = v4i32{tf->m32T[lane][0], tf->m32T[lane][1], tf->m32T[lane][2], tf->m32T[lane][3]};
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        G[t] = tf->m32G[t][lane];
+        WM[t] = tf->m32R[t][lane] < r ? tf->m32W[t][lane] : 0.0f;
+      }
+      loaded = tid;
+      loaded_r = r;
+    }
+    const int N = __builtin_amdgcn_readfirstlane(as_constant(tf)->N);
+    const int D = __builtin_amdgcn_readfirstlane(im->D);
+    uint32_t keep = 0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t)
+      if (kap(t, 0) % N < D || kap(t, 1) % N < D) keep |= 1u << t;
+    keep = __builtin_amdgcn_readfirstlane(keep);
+    const int H = __builtin_amdgcn_readfirstlane(im->H), W = __builtin_amdgcn_readfirstlane(im->W);
+    const int ps = __builtin_amdgcn_readfirstlane(im->ps), pd = __builtin_amdgcn_readfirstlane(im->pd);
+    const int rw = __builtin_amdgcn_readfirstlane(im->bw);
+    uint8_t* const dst = im->dst;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(im->src), 0, (H - 1) * ps + W, kRegionFlags);
+    const __amdgpu_buffer_rsrc_t rd =
+        __builtin_amdgcn_make_buffer_rsrc(dst, 0, dst ? (H - 1) * pd + W : 0, kRegionFlags);
+    const int tb = im->tile_blocks, nreg = im->nblocks;
+    const int g0 = (tile - im->tile0) * tb;
+    const int g1 = g0 + tb < nreg ? g0 + tb : nreg;
+    uint32_t sxx = 0, sxy = 0;
+    // the next region's pixels are loaded while the current one is coded
+    RegionRows nrr = region_rows(g0 + wave, rw, H, W, ps, pd, c, h, g0 + wave < g1);
+    uint32_t nx[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
+    for (int g = g0 + wave; g < g1; g += 4) {
+      const RegionRows cur = nrr;
+      uint32_t x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = nx[q];
+      nrr = region_rows(g + 4, rw, H, W, ps, pd, c, h, g + 4 < g1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
+      // row stage on pixel - 128 (xor 0x80 makes the bytes signed)
+      const v4i32 X = {static_cast<int>(x[0] ^ 0x80808080u), static_cast<int>(x[1] ^ 0x80808080u),
+                       static_cast<int>(x[2] ^ 0x80808080u), static_cast<int>(x[3] ^ 0x80808080u)};
+      const v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
+      // column stage on the signed bytes of Y
+      v4i32 lo, hi;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        uint32_t wl = 0, wh = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int y = Y[4 * w + b];
+          const int l8 = static_cast<int>(static_cast<int8_t>(y & 0xff));
+          const int h8 = (y - l8) >> 8;
+          wl |= (static_cast<uint32_t>(l8) & 0xffu) << (8 * b);
+          wh |= (static_cast<uint32_t>(h8) & 0xffu) << (8 * b);
+        }
+        lo[w] = static_cast<int>(wl);
+        hi[w] = static_cast<int>(wh);
+      }
+      const v16i32 Bl = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, Tw, zi, 0, 0, 0);
+      const v16i32 Bh = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, Tw, zi, 0, 0, 0);
+      // register t: B[c][kap(t, h)], scaled and masked
+      float Bs[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) Bs[t] = static_cast<float>(Bh[t] * 256 + Bl[t]) * WM[t];
+      // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
+      v16f32 Z = zf;
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (keep & (1u << t)) Z = __builtin_amdgcn_mfma_f32_32x32x2f32(Bs[t], G[t], Z, 0, 0, 0);
+      v16f32 O = zf;
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (keep & (1u << t)) O = __builtin_amdgcn_mfma_f32_32x32x2f32(Z[t], G[t], O, 0, 0, 0);
+      // register t of O: A'[c][kap(t, h)] - 128
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v] + 128.5f), v, word);
+        __builtin_amdgcn_raw_buffer_store_b32(word, rd, cur.od[q], 0, 0);
+        if (cur.ok[q]) {
+          sxx = __builtin_amdgcn_udot4(x[q], x[q], sxx, false);
+          sxx = __builtin_amdgcn_udot4(word, word, sxx, false);
+          sxy = __builtin_amdgcn_udot4(x[q], word, sxy, false);
+        }
+      }
+    }
+    reduce_and_finish(static_cast<unsigned long long>(sxx - 2u * sxy), red, a.res + im->slot, 1, im->ntiles,
+                      static_cast<long long>(H) * W);
+  }
+}
+
+}  // namespace
+
+rklt_status launch_mfma32(const KArgs& a, int grid, void* stream) {
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (a.imgs) hipLaunchKernelGGL(rklt_mfma32_kernel<true>, dim3(grid), dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(rklt_mfma32_kernel<false>, dim3(grid), dim3(256), 0, st, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RKLT_E_HIP, "rklt_mfma32_kernel: launch failed: %s", hipGetErrorString(e));
+  return RKLT_OK;
+}
+
+}  // namespace rklt

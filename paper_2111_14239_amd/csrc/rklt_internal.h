@@ -91,6 +91,22 @@ struct alignas(256) DevTransform {
   // Q~ = Q / (s s^T); qstep = fl32(Q_ij); at i*N + j
   float qinv[RKLT_MAX_N * RKLT_MAX_N];
   float qstep[RKLT_MAX_N * RKLT_MAX_N];
+  // N in {16, 32} matrix-core kernel (m32_ok = 1 when it takes the
+  // transform): a wave codes a 32 x 32 pixel region, one N = 32 block or
+  // 2 x 2 N = 16 blocks, with Tb = T on the block diagonal (zero elsewhere)
+  // and Gb likewise for T_hat^-1.  With h = lane / 32, c = lane % 32 and
+  // kap(t, h) = 8 (t / 4) + 4 h + t % 4 (the row of accumulator register t):
+  //   m32T[lane][w]  int8x4 words, byte e of word w = Tb[c][kap(4w + e, h)]:
+  //                  B operand of both int8 stages (row and column);
+  //   m32G[t][lane]  Gb[c][kap(t, h)]: B operand of both FP32 inverse stages;
+  //   m32W[t][lane]  s_i s_j of region coefficient (c, kap(t, h)), which is
+  //                  coefficient (c % N, kap(t, h) % N) of one of the region's
+  //                  blocks; m32R[t][lane] its zig-zag rank.
+  int32_t m32_ok, m32_pad[3];
+  int32_t m32T[64][4];
+  float m32G[16][64];
+  float m32W[16][64];
+  int16_t m32R[16][64];
 };
 
 // One image of a launch (device memory for a plan, a kernel argument for the
@@ -183,6 +199,16 @@ struct MsArgs {
 };
 constexpr int kMsTileW = 64, kMsTileH = 32;
 rklt_status launch_mssim(const MsArgs& a, int grid, void* stream);
+
+// The N in {16, 32} matrix-core kernel codes 32 x 32 pixel regions: its
+// block index space is the grid of regions, ceil(H / 32) rows of
+// ceil(W / 32) (regions past the image edge are partly out of range).
+inline void mfma32_regions(DevImage& d) {
+  d.bw = (d.W + 31) / 32;
+  d.bwp = d.bw;
+  d.nblocks = ((d.H + 31) / 32) * d.bw;
+}
+rklt_status launch_mfma32(const KArgs& a, int grid, void* stream);
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
 int panel_blocks(int N);  // blocks of one panel of the panel kernel
 constexpr int kMaxTilesPerImage = 65535;  // tile count field of the packed accumulator

@@ -1,0 +1,149 @@
+"""GPU parity of the N in {16, 32} matrix-core kernel (32 x 32 regions:
+one N = 32 block or 2 x 2 N = 16 blocks) against the oracle, through the
+C ABI.
+
+Bars: the forward transform is exact int32 inside the kernel and the inverse
+FP32, so reconstructed pixels are at most 1 LSB from the oracle's
+exact-rational reconstruction and differ only where the oracle's value lies
+within TIE_BAND of a rounding tie; SSE equals the returned reconstruction's;
+PSNR within the tie tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import rklt_oracle as o
+from paper_2111_14239_amd import rklt
+from paper_2111_14239_amd.inputs import ar1_image, random_image
+
+pytestmark = pytest.mark.gpu
+
+TIE_BAND = {16: 5e-3, 32: 1e-2}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = rklt.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def alpha8(N, rho):
+    return 8.0 / float(np.max(np.abs(o.klt(N, rho))))
+
+
+def check(img, N, rho, alpha, r, got_rec, got, ell=128):
+    ref = o.codec(img, N, rho, alpha, r, ell)
+    diff = got_rec.astype(np.int64) - ref["recon"].astype(np.int64)
+    assert np.max(np.abs(diff)) <= 1
+    if np.any(diff):
+        frac = ref["pre_round"] - np.floor(ref["pre_round"])
+        near = np.abs(frac - 0.5) <= TIE_BAND[N]
+        assert np.all(near[diff != 0]), "a pixel away from a rounding tie differs"
+    e = img.astype(np.int64) - got_rec.astype(np.int64)
+    assert got["sse"] == int(np.sum(e * e))
+    if ref["sse"] == 0:
+        assert got["sse"] == 0 and math.isinf(got["psnr_db"])
+    else:
+        assert got["psnr_db"] == pytest.approx(o.psnr_from_mse(got["sse"] / img.size), abs=1e-4)
+        frac = ref["pre_round"] - np.floor(ref["pre_round"])
+        near = np.abs(frac - 0.5) <= TIE_BAND[N]
+        ee = np.abs(img.astype(np.int64) - ref["recon"].astype(np.int64))[near]
+        dsse = int(np.sum(2 * ee + 1))
+        tol = 1e-3 if dsse == 0 else max(1e-3, 10 * math.log10((ref["sse"] + dsse) / max(ref["sse"] - dsse, 1)))
+        assert got["psnr_db"] == pytest.approx(ref["psnr"], abs=tol)
+    return int(np.count_nonzero(diff))
+
+
+def run_plan(ctx, imgs, tids, rs, ells=None):
+    ells = ells or [128] * len(imgs)
+    xs = [torch.from_numpy(im).cuda() for im in imgs]
+    ds = [rklt.empty_pitched(im.shape[0], im.shape[1]) for im in imgs]
+    plan = ctx.plan([rklt.image_desc(x, t, r, dst=d, level_shift=l) for x, d, t, r, l in zip(xs, ds, tids, rs, ells)])
+    res = rklt.new_results(len(imgs))
+    plan.run(int(res.data_ptr()))
+    torch.cuda.synchronize()
+    out = rklt.read_results(res)
+    recs = [d.cpu().numpy() for d in ds]
+    per = plan.images_per_class
+    plan.close()
+    return recs, out, per
+
+
+@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("rho", [0.9, 0.5])
+def test_region_kernel_matches_oracle(ctx, N, rho):
+    alphas = [alpha8(N, rho)] + ([4.0] if N == 16 else [12.0])
+    # several regions with a ragged region row and column (N = 16: sides
+    # that are not multiples of 32)
+    H, W = (80, 208) if N == 16 else (96, 160)
+    img = ar1_image(H, W, rho, seed=N)
+    for alpha in alphas:
+        tid = ctx.transform_id(N, rho, alpha)
+        rs = sorted({1, 3, N * N // 4, math.ceil(10 * N * N / 64), N * N})
+        recs, out, per = run_plan(ctx, [img] * len(rs), [tid] * len(rs), rs)
+        assert per[4] == len(rs), per
+        for r, rec, got in zip(rs, recs, out):
+            check(img, N, rho, alpha, r, rec, got)
+
+
+def test_plain_path_and_random_pixels(ctx):
+    for N in (16, 32):
+        tid = ctx.transform_id(N, 0.9, alpha8(N, 0.9))
+        img = random_image(3 * N, 5 * N, seed=N + 1)
+        x = torch.from_numpy(img).cuda()
+        d = torch.empty_like(x)
+        res = rklt.new_results(1)
+        for r in (1, N * N // 2, N * N):
+            ctx.codec(rklt.image_desc(x, tid, r, dst=d), int(res.data_ptr()))
+            torch.cuda.synchronize()
+            check(img, N, 0.9, alpha8(N, 0.9), r, d.cpu().numpy(), rklt.read_results(res)[0])
+
+
+def test_mixed_classes_in_one_plan(ctx):
+    # N = 16: level shift 128 on the region kernel, level shift 0 and a
+    # transform beyond its bounds (alpha 100: row sums of |T| beyond 255)
+    # on the panel kernel
+    N = 16
+    a8 = alpha8(N, 0.9)
+    t8 = ctx.transform_id(N, 0.9, a8)
+    tbig = ctx.transform_id(N, 0.9, 100.0)
+    imgs = [ar1_image(64, 96, 0.9, seed=3), ar1_image(48, 112, 0.7, seed=4), ar1_image(32, 48, 0.9, seed=5)]
+    recs, out, per = run_plan(ctx, imgs, [t8, t8, tbig], [40, 64, 40], [128, 0, 128])
+    assert per[4] == 1 and per[0] == 2, per
+    for (img, al, r, ell), rec, got in zip(zip(imgs, [a8, a8, 100.0], [40, 64, 40], [128, 0, 128]), recs, out):
+        check(img, N, 0.9, al, r, rec, got, ell)
+
+
+def test_full_size_sampled(ctx):
+    # 2048 x 2048 images (the block-size workload), each checked on strips of
+    # block rows at the top and bottom against the oracle, SSE in full
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    for N, r in ((16, 40), (32, 1024)):
+        alpha = alpha8(N, 0.9)
+        tid = ctx.transform_id(N, 0.9, alpha)
+        xs = [torch.randint(0, 256, (2048, 2048), dtype=torch.uint8, device="cuda", generator=gen) for _ in range(2)]
+        ds = [torch.empty_like(x) for x in xs]
+        plan = ctx.plan([rklt.image_desc(x, tid, r, dst=d) for x, d in zip(xs, ds)])
+        assert plan.images_per_class[4] == 2
+        res = rklt.new_results(2)
+        plan.run(int(res.data_ptr()))
+        torch.cuda.synchronize()
+        out = rklt.read_results(res)
+        for x, d, got in zip(xs, ds, out):
+            img, rec = x.cpu().numpy(), d.cpu().numpy()
+            e = img.astype(np.int64) - rec.astype(np.int64)
+            assert got["sse"] == int(np.sum(e * e))
+            for y0 in (0, 2048 - N):
+                ref = o.codec(img[y0:y0 + N], N, 0.9, alpha, r, 128)
+                diff = rec[y0:y0 + N].astype(np.int64) - ref["recon"].astype(np.int64)
+                assert np.max(np.abs(diff)) <= 1
+                frac = ref["pre_round"] - np.floor(ref["pre_round"])
+                assert np.all((np.abs(frac - 0.5) <= TIE_BAND[N])[diff != 0])
+        plan.close()
