@@ -25,6 +25,11 @@ COMMON = [
 ]
 
 
+# per-file flags: the N in {16, 32} matrix-core kernel keeps its accumulators
+# in ordinary VGPRs (no accumulator-register copies; one more wave per SIMD)
+PER_FILE = {"codec_mfma32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _hipcc() -> str:
     for c in ("/opt/rocm/bin/hipcc", "hipcc"):
         if os.path.exists(c) or c == "hipcc":
@@ -53,7 +58,8 @@ def build(verbose: bool = False, out: str = LIB, defines: tuple = ()) -> str:
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"]
         defs = [f"-D{d}" for d in defines]
-        jobs.append(([hipcc, *lang, *COMMON, *defs, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+        extra = PER_FILE.get(src, [])
+        jobs.append(([hipcc, *lang, *COMMON, *extra, *defs, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         outs = list(ex.map(lambda j: _run(j[0]), jobs))
     if verbose:

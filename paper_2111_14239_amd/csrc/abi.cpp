@@ -523,7 +523,10 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
       for (int tt = 0; tt < 16; ++tt) {
         const int j = kap(tt, h);
         const bool diag = c / N == j / N;
-        dt.m32G[tt][lane] = diag ? static_cast<float>(t->G[(c % N) * N + j % N]) : 0.0f;
+        const double gv = diag ? t->G[(c % N) * N + j % N] : 0.0;
+        const _Float16 ghi = static_cast<_Float16>(gv);
+        dt.m32Gs[tt / 8][0][lane][tt % 8] = ghi;
+        dt.m32Gs[tt / 8][1][lane][tt % 8] = static_cast<_Float16>(gv - static_cast<double>(ghi));
         // coefficient (c, j) of the region is coefficient (c % N, j % N) of
         // one of its blocks (all four quadrants hold coefficients)
         dt.m32W[tt][lane] = static_cast<float>(t->s[c % N] * t->s[j % N]);

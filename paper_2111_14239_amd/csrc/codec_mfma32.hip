@@ -8,10 +8,13 @@
 //   column stage   B^T = Y^T Tb^T                two v_mfma_i32_32x32x32_i8
 //                  (Y = 256 hi + lo, hi and lo signed bytes: |Y| <= 128 L1)
 //   zonal + S      B_hat = (s_i s_j) B on the first r zig-zag positions, FP32
-//   inverse        Z = B_hat Gb^T, A'^T = Z^T Gb^T  v_mfma_f32_32x32x2_f32
-//                  (Gb = T_hat^-1 on the block diagonal)
+//   inverse        Z = B_hat Gb^T, A'^T = Z^T Gb^T  v_mfma_f32_32x32x16_f16
+//                  (Gb = T_hat^-1 on the block diagonal; each FP32 operand
+//                  as two fp16 parts x = hi + lo, 22 bits, and the products
+//                  hi hi + hi lo + lo hi accumulated in FP32)
 //   pixel          clip(floor(A' + 128 + 1/2)), squared error
-// so B = T (A - 128) T^T is exact int32 and the inverse is FP32.
+// so B = T (A - 128) T^T is exact int32 and the inverse is FP32 up to the
+// dropped lo lo terms (relative 2^-22).
 //
 // Layouts.  With h = lane / 32 and c = lane % 32, accumulator register t of
 // lane l holds row kap(t, h) = 8 (t / 4) + 4 h + t % 4, column c; an int8
@@ -19,16 +22,17 @@
 // operand lane one K element (h).  The K order of a product only has to
 // agree between its two operands, so every stage reads the previous stage's
 // accumulator registers as they are: K element e of lane l is index
-// kap(e, h), and the tables m32T, m32G of the transform record hold Tb and
-// Gb in that order.  Lane l loads row c of the region at the pixel columns
+// kap(e, h), and the tables m32T, m32Gs of the transform record hold Tb
+// and Gb in that order (an fp16 operand lane holds 8 K elements: chunk k of
+// a product takes registers 8k .. 8k + 7).  Lane l loads row c of the region at the pixel columns
 // kap(0..15, h) (four 32-bit words at columns 8q + 4h), and the last product
 // returns exactly those pixels of the reconstruction to it, so the store and
 // the squared error need no exchange.
 //
-// Truncation: a step t of the inverse products carries columns (then rows)
+// Truncation: register t of the inverse operands carries columns (then rows)
 // kap(t, 0) and kap(t, 1); when both are >= D modulo N (D anti-diagonals
-// hold every kept coefficient) all its coefficients are zero and the step is
-// skipped.
+// hold every kept coefficient) its coefficients are zero, and a K chunk whose
+// eight registers are all zero is skipped.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -42,6 +46,27 @@ namespace {
 typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
 typedef float v16f32 __attribute__((ext_vector_type(16)));
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef _Float16 v8f16 __attribute__((ext_vector_type(8)));
+
+// Eight FP32 values as two fp16 parts: hi = x rounded toward zero, lo = the
+// (exact) remainder x - hi rounded toward zero; hi + lo carries 22 bits.
+__device__ __forceinline__ void split_parts(const float* x, v8f16& hi, v8f16& lo) {
+  v4u32 wh, wl;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const auto h2 = __builtin_amdgcn_cvt_pkrtz(x[2 * p], x[2 * p + 1]);
+    const float r0 = x[2 * p] - static_cast<float>(h2[0]);
+    const float r1 = x[2 * p + 1] - static_cast<float>(h2[1]);
+    wh[p] = __builtin_bit_cast(uint32_t, h2);
+    wl[p] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r0, r1));
+  }
+  hi = __builtin_bit_cast(v8f16, wh);
+  lo = __builtin_bit_cast(v8f16, wl);
+}
+
+// Waves per workgroup; they take consecutive regions.
+constexpr int kM32Waves = 4;
 
 constexpr uint32_t kRegionOut = 0x80000000u;  // out-of-range buffer offset: zero load, dropped store
 constexpr int kRegionFlags = 0x00020000;
@@ -70,15 +95,16 @@ __device__ __forceinline__ RegionRows region_rows(int g, int rw, int H, int W, i
 }
 
 template <bool PLAN>
-__global__ __launch_bounds__(256) void rklt_mfma32_kernel(KArgs a) {
-  __shared__ unsigned long long red[4];
+__global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
+  __shared__ unsigned long long red[kM32Waves];
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   int loaded = -1, loaded_r = -1;
   v4i32 Tw = {0, 0, 0, 0};
-  float G[16], WM[16];
+  float WM[16];
+  v8f16 Gh[2] = {}, Gl[2] = {};
 #pragma unroll
-  for (int t = 0; t < 16; ++t) G[t] = WM[t] = 0.0f;
+  for (int t = 0; t < 16; ++t) WM[t] = 0.0f;
   const v16i32 zi = {};
   const v16f32 zf = {};
   const ConstInt tile_img = (ConstInt)(a.tile_img);
@@ -92,9 +118,11 @@ __global__ __launch_bounds__(256) void rklt_mfma32_kernel(KArgs a) {
       // per-lane operands of the transform; weights of ranks >= r zeroed
       Tw = v4i32{tf->m32T[lane][0], tf->m32T[lane][1], tf->m32T[lane][2], tf->m32T[lane][3]};
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        G[t] = tf->m32G[t][lane];
-        WM[t] = tf->m32R[t][lane] < r ? tf->m32W[t][lane] : 0.0f;
+      for (int t = 0; t < 16; ++t) WM[t] = tf->m32R[t][lane] < r ? tf->m32W[t][lane] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        Gh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][0][lane][0]);
+        Gl[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][1][lane][0]);
       }
       loaded = tid;
       loaded_r = r;
@@ -123,12 +151,12 @@ __global__ __launch_bounds__(256) void rklt_mfma32_kernel(KArgs a) {
     uint32_t nx[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
-    for (int g = g0 + wave; g < g1; g += 4) {
+    for (int g = g0 + wave; g < g1; g += kM32Waves) {
       const RegionRows cur = nrr;
       uint32_t x[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) x[q] = nx[q];
-      nrr = region_rows(g + 4, rw, H, W, ps, pd, c, h, g + 4 < g1);
+      nrr = region_rows(g + kM32Waves, rw, H, W, ps, pd, c, h, g + kM32Waves < g1);
 #pragma unroll
       for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
       // row stage on pixel - 128 (xor 0x80 makes the bytes signed)
@@ -158,20 +186,38 @@ __global__ __launch_bounds__(256) void rklt_mfma32_kernel(KArgs a) {
 #pragma unroll
       for (int t = 0; t < 16; ++t) Bs[t] = static_cast<float>(Bh[t] * 256 + Bl[t]) * WM[t];
       // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
-      v16f32 Z = zf;
+      // O starts at 128 + 1/2: the level shift and the rounding offset
+      const v16f32 half_up = {128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f,
+                              128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f};
+      v16f32 Z = zf, O = half_up;
+      // K chunk k holds registers 8k .. 8k + 7 (skipped when all of them are)
 #pragma unroll
-      for (int t = 0; t < 16; ++t)
-        if (keep & (1u << t)) Z = __builtin_amdgcn_mfma_f32_32x32x2f32(Bs[t], G[t], Z, 0, 0, 0);
-      v16f32 O = zf;
+      for (int k = 0; k < 2; ++k)
+        if ((keep >> (8 * k)) & 0xffu) {
+          v8f16 ah, al;
+          split_parts(&Bs[8 * k], ah, al);
+          Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Gh[k], Z, 0, 0, 0);
+          Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Gl[k], Z, 0, 0, 0);
+          Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Gh[k], Z, 0, 0, 0);
+        }
+      float Zr[16];
 #pragma unroll
-      for (int t = 0; t < 16; ++t)
-        if (keep & (1u << t)) O = __builtin_amdgcn_mfma_f32_32x32x2f32(Z[t], G[t], O, 0, 0, 0);
-      // register t of O: A'[c][kap(t, h)] - 128
+      for (int t = 0; t < 16; ++t) Zr[t] = Z[t];
+#pragma unroll
+      for (int k = 0; k < 2; ++k)
+        if ((keep >> (8 * k)) & 0xffu) {
+          v8f16 ah, al;
+          split_parts(&Zr[8 * k], ah, al);
+          O = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Gh[k], O, 0, 0, 0);
+          O = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Gl[k], O, 0, 0, 0);
+          O = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Gh[k], O, 0, 0, 0);
+        }
+      // register t of O: A'[c][kap(t, h)] + 1/2
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         uint32_t word = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v] + 128.5f), v, word);
+        for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v]), v, word);
         __builtin_amdgcn_raw_buffer_store_b32(word, rd, cur.od[q], 0, 0);
         if (cur.ok[q]) {
           sxx = __builtin_amdgcn_udot4(x[q], x[q], sxx, false);
@@ -189,8 +235,8 @@ __global__ __launch_bounds__(256) void rklt_mfma32_kernel(KArgs a) {
 
 rklt_status launch_mfma32(const KArgs& a, int grid, void* stream) {
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  if (a.imgs) hipLaunchKernelGGL(rklt_mfma32_kernel<true>, dim3(grid), dim3(256), 0, st, a);
-  else hipLaunchKernelGGL(rklt_mfma32_kernel<false>, dim3(grid), dim3(256), 0, st, a);
+  if (a.imgs) hipLaunchKernelGGL(rklt_mfma32_kernel<true>, dim3(grid), dim3(64 * kM32Waves), 0, st, a);
+  else hipLaunchKernelGGL(rklt_mfma32_kernel<false>, dim3(grid), dim3(64 * kM32Waves), 0, st, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RKLT_E_HIP, "rklt_mfma32_kernel: launch failed: %s", hipGetErrorString(e));
   return RKLT_OK;

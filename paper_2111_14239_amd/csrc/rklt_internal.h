@@ -98,15 +98,17 @@ struct alignas(256) DevTransform {
   // kap(t, h) = 8 (t / 4) + 4 h + t % 4 (the row of accumulator register t):
   //   m32T[lane][w]  int8x4 words, byte e of word w = Tb[c][kap(4w + e, h)]:
   //                  B operand of both int8 stages (row and column);
-  //   m32G[t][lane]  Gb[c][kap(t, h)]: B operand of both FP32 inverse stages;
   //   m32W[t][lane]  s_i s_j of region coefficient (c, kap(t, h)), which is
   //                  coefficient (c % N, kap(t, h) % N) of one of the region's
   //                  blocks; m32R[t][lane] its zig-zag rank.
+  //   m32Gs[k][p][lane][e]  Gb[c][kap(8k + e, h)] as two fp16 parts (p = 0:
+  //                  Gb rounded to fp16, p = 1: the rest rounded to fp16): B
+  //                  operands of both inverse stages.
   int32_t m32_ok, m32_pad[3];
   int32_t m32T[64][4];
-  float m32G[16][64];
   float m32W[16][64];
   int16_t m32R[16][64];
+  _Float16 m32Gs[2][2][64][8];
 };
 
 // One image of a launch (device memory for a plan, a kernel argument for the

@@ -147,3 +147,28 @@ def test_full_size_sampled(ctx):
                 frac = ref["pre_round"] - np.floor(ref["pre_round"])
                 assert np.all((np.abs(frac - 0.5) <= TIE_BAND[N])[diff != 0])
         plan.close()
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_precision_of_the_region_inverse(ctx, N):
+    # the two-part fp16 inverse against the oracle's exact rational
+    # reconstruction on 256 x 256 AR(1) images: every differing pixel lies
+    # within the tie band, few differ, and the figures are printed (-s)
+    rho = 0.9
+    a = alpha8(N, rho)
+    tid = ctx.transform_id(N, rho, a)
+    stats = []
+    for r in sorted({1, math.ceil(10 * N * N / 64), N * N // 4, N * N}):
+        img = ar1_image(256, 256, rho, seed=700 + N + r)
+        recs, out, per = run_plan(ctx, [img], [tid], [r])
+        assert per[4] == 1
+        ref = o.codec(img, N, rho, a, r, 128)
+        check(img, N, rho, a, r, recs[0], out[0])
+        diff = recs[0].astype(np.int64) - ref["recon"].astype(np.int64)
+        frac = ref["pre_round"] - np.floor(ref["pre_round"])
+        off = int(np.count_nonzero(diff))
+        stats.append((r, off / diff.size, float(np.max(np.abs(frac - 0.5)[diff != 0], initial=0.0)),
+                      abs(out[0]["psnr_db"] - ref["psnr"])))
+        assert off / diff.size <= 2e-3
+    print(f"\nN={N} region kernel: (r, share of pixels off by one, largest |x - tie| among them, |dPSNR| dB)",
+          [(r, f"{s:.2e}", f"{t:.1e}", f"{p:.1e}") for r, s, t, p in stats])
