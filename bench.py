@@ -277,7 +277,7 @@ def block_sizes(ctx, steps: int) -> dict:
             out[f"N{N}_r{r}"] = {"ms_per_launch": ms, "value": pixels / (ms / 1e3) / 1e6, "unit": "Mpixel/s",
                                  "hbm_frac": BYTES_PER_PIXEL * pixels / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                                  "alpha": alpha, "launches": plan.launches,
-                                 "kernel_class": "matrix_core_n16_32" if plan.images_per_class[4] else "panel"}
+                                 "kernel_class": "matrix_core_region" if plan.images_per_class[4] else "panel"}
             plan.close()
         del srcs, dsts
     return out
@@ -487,7 +487,7 @@ def main():
             "images": n, "rejected_alpha1": rejected, "pixels": pixels,
             "tiles": plan.tiles, "grid_wgs": plan.grid, "launches_per_step": plan.launches,
             "images_per_kernel_class": dict(zip(("panel", "register_n8", "matrix_core_n8", "panel_float",
-                                                 "matrix_core_n16_32"),
+                                                 "matrix_core_region"),
                                                 plan.images_per_class)),
             "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 4,
         },

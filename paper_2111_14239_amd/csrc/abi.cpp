@@ -84,12 +84,20 @@ bool block8_fits(const DevTransform& t, int ell) {
   return ell == 128 && t.N == 8 && t.max_abs <= 127 && 128 * t.max_row_l1 <= 32767;
 }
 
+// The region kernel splits the corrected row sums Y = (A - 128) T^T +
+// (128 - ell) sig into two signed bytes: |Y| <= 128 L1 + |128 - ell| max|sig|
+// must stay within 32640.
+bool region_fits(const DevTransform& t, int ell) {
+  const int lift = 128 - ell;
+  return t.m32_ok && 128 * t.max_row_l1 + (lift < 0 ? -lift : lift) * t.m32_sig <= 32640;
+}
+
 int kernel_class(const DevTransform& t, int ell, bool dump) {
   if (t.is_float) return 3;
   if (t.quant) return 0;
-  if (t.m32_ok && ell == 128 && !dump) return 4;
-  if (!block8_fits(t, ell)) return 0;
-  return (t.m_ok && !dump) ? 2 : 1;
+  if (block8_fits(t, ell)) return (t.m_ok && !dump) ? 2 : 1;
+  if (!dump && region_fits(t, ell)) return 4;
+  return 0;
 }
 
 hipError_t use_device(int device) {
@@ -504,13 +512,15 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
     }
   }
 
-  if ((N == 16 || N == 32) && max_abs <= 127 && 128 * max_l1 <= 32640) {
-    // N in {16, 32} matrix-core operands (layout in DevTransform): Tb and Gb
-    // on the block diagonal of a 32 x 32 region, K order kap(e, h)
+  if (max_abs <= 127 && 128 * max_l1 <= 32640) {
+    // region matrix-core operands (layout in DevTransform): Tb and Gb on the
+    // block diagonal of a 32 x 32 region, K order kap(e, h)
     auto kap = [](int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); };
     dt.m32_ok = 1;
+    for (int i = 0; i < N; ++i) dt.m32_sig = std::max(dt.m32_sig, std::abs(dt.sig[i]));
     for (int lane = 0; lane < 64; ++lane) {
       const int h = lane >> 5, c = lane & 31;
+      dt.m32S[lane] = dt.sig[c % N];
       for (int w = 0; w < 4; ++w) {
         uint32_t word = 0;
         for (int b = 0; b < 4; ++b) {

@@ -1,19 +1,21 @@
-// Matrix-core kernel of the codec for block lengths N in {16, 32} (§4.1,
-// Appendix A; level shift 128, |T_ij| <= 127 and 128 L1 < 32640 with L1 the
-// largest row sum of |T|).  A wave codes one 32 x 32 pixel region per step:
-// one N = 32 block, or 2 x 2 N = 16 blocks through the block-diagonal Tb
-// (T twice on the diagonal; the off-diagonal products are zero, so the
-// blocks stay independent).  Every stage is a 32 x 32 x 32 product:
-//   row stage      Y  = (A - 128) Tb^T           v_mfma_i32_32x32x32_i8
+// Region matrix-core kernel of the codec (§4.1, Appendix A) for block
+// lengths N in {4, 8, 16, 32} and any level shift ell, for T with |T_ij| <=
+// 127 and 128 L1 + |128 - ell| max|sig| <= 32640 (L1 the largest row sum of
+// |T|, sig_j the row sums of T).  A wave codes one 32 x 32 pixel region per
+// step: (32 / N)^2 blocks through the block-diagonal Tb (T on the diagonal;
+// the off-diagonal products are zero, so the blocks stay independent).
+// Every stage is a 32 x 32 x 32 product:
+//   row stage      Y  = (A - 128) Tb^T + (128 - ell) sig   v_mfma_i32_32x32x32_i8
+//                  (the row sums of A - ell, from signed pixel bytes)
 //   column stage   B^T = Y^T Tb^T                two v_mfma_i32_32x32x32_i8
-//                  (Y = 256 hi + lo, hi and lo signed bytes: |Y| <= 128 L1)
+//                  (Y = 256 hi + lo, hi and lo signed bytes)
 //   zonal + S      B_hat = (s_i s_j) B on the first r zig-zag positions, FP32
 //   inverse        Z = B_hat Gb^T, A'^T = Z^T Gb^T  v_mfma_f32_32x32x16_f16
 //                  (Gb = T_hat^-1 on the block diagonal; each FP32 operand
 //                  as two fp16 parts x = hi + lo, 22 bits, and the products
 //                  hi hi + hi lo + lo hi accumulated in FP32)
-//   pixel          clip(floor(A' + 128 + 1/2)), squared error
-// so B = T (A - 128) T^T is exact int32 and the inverse is FP32 up to the
+//   pixel          clip(floor(A' + ell + 1/2)), squared error
+// so B = T (A - ell) T^T is exact int32 and the inverse is FP32 up to the
 // dropped lo lo terms (relative 2^-22).
 //
 // Layouts.  With h = lane / 32 and c = lane % 32, accumulator register t of
@@ -87,7 +89,7 @@ __device__ __forceinline__ RegionRows region_rows(int g, int rw, int H, int W, i
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int col = rx * 32 + 8 * q + 4 * h;
-    rr.ok[q] = in_tile && row < H && col < W;  // W is a multiple of 16: a word is all in or all out
+    rr.ok[q] = in_tile && row < H && col < W;  // W is a multiple of 4: a word is all in or all out
     rr.os[q] = rr.ok[q] ? static_cast<uint32_t>(row) * ps + col : kRegionOut;
     rr.od[q] = rr.ok[q] ? static_cast<uint32_t>(row) * pd + col : kRegionOut;
   }
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   int loaded = -1, loaded_r = -1;
   v4i32 Tw = {0, 0, 0, 0};
+  int S = 0;  // sig of this lane's region column
   float WM[16];
   v8f16 Gh[2] = {}, Gl[2] = {};
 #pragma unroll
@@ -117,6 +120,7 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     if (tid != loaded || r != loaded_r) {
       // per-lane operands of the transform; weights of ranks >= r zeroed
       Tw = v4i32{tf->m32T[lane][0], tf->m32T[lane][1], tf->m32T[lane][2], tf->m32T[lane][3]};
+      S = tf->m32S[lane];
 #pragma unroll
       for (int t = 0; t < 16; ++t) WM[t] = tf->m32R[t][lane] < r ? tf->m32W[t][lane] : 0.0f;
 #pragma unroll
@@ -129,6 +133,9 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     }
     const int N = __builtin_amdgcn_readfirstlane(as_constant(tf)->N);
     const int D = __builtin_amdgcn_readfirstlane(im->D);
+    const int ell = __builtin_amdgcn_readfirstlane(im->ell);
+    const int lift = (128 - ell) * S;  // row-sum correction of this lane's column
+    const float out_bias = static_cast<float>(ell) + 0.5f;
     uint32_t keep = 0;
 #pragma unroll
     for (int t = 0; t < 16; ++t)
@@ -162,7 +169,11 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       // row stage on pixel - 128 (xor 0x80 makes the bytes signed)
       const v4i32 X = {static_cast<int>(x[0] ^ 0x80808080u), static_cast<int>(x[1] ^ 0x80808080u),
                        static_cast<int>(x[2] ^ 0x80808080u), static_cast<int>(x[3] ^ 0x80808080u)};
-      const v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
+      v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
+      if (ell != 128) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Y[t] += lift;
+      }
       // column stage on the signed bytes of Y
       v4i32 lo, hi;
 #pragma unroll
@@ -186,10 +197,7 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
 #pragma unroll
       for (int t = 0; t < 16; ++t) Bs[t] = static_cast<float>(Bh[t] * 256 + Bl[t]) * WM[t];
       // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
-      // O starts at 128 + 1/2: the level shift and the rounding offset
-      const v16f32 half_up = {128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f,
-                              128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f, 128.5f};
-      v16f32 Z = zf, O = half_up;
+      v16f32 Z = zf, O = zf;
       // K chunk k holds registers 8k .. 8k + 7 (skipped when all of them are)
 #pragma unroll
       for (int k = 0; k < 2; ++k)
@@ -212,12 +220,13 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
           O = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Gl[k], O, 0, 0, 0);
           O = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Gh[k], O, 0, 0, 0);
         }
-      // register t of O: A'[c][kap(t, h)] + 1/2
+      // register t of O: A'[c][kap(t, h)] - ell
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         uint32_t word = 0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v]), v, word);
+        for (int v = 0; v < 4; ++v)
+          word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v] + out_bias), v, word);
         __builtin_amdgcn_raw_buffer_store_b32(word, rd, cur.od[q], 0, 0);
         if (cur.ok[q]) {
           sxx = __builtin_amdgcn_udot4(x[q], x[q], sxx, false);

@@ -91,10 +91,10 @@ struct alignas(256) DevTransform {
   // Q~ = Q / (s s^T); qstep = fl32(Q_ij); at i*N + j
   float qinv[RKLT_MAX_N * RKLT_MAX_N];
   float qstep[RKLT_MAX_N * RKLT_MAX_N];
-  // N in {16, 32} matrix-core kernel (m32_ok = 1 when it takes the
-  // transform): a wave codes a 32 x 32 pixel region, one N = 32 block or
-  // 2 x 2 N = 16 blocks, with Tb = T on the block diagonal (zero elsewhere)
-  // and Gb likewise for T_hat^-1.  With h = lane / 32, c = lane % 32 and
+  // region matrix-core kernel (m32_ok = 1 when it can take the transform):
+  // a wave codes a 32 x 32 pixel region, (32 / N)^2 blocks of N in
+  // {4, 8, 16, 32}, with Tb = T on the block diagonal (zero elsewhere) and
+  // Gb likewise for T_hat^-1.  With h = lane / 32, c = lane % 32 and
   // kap(t, h) = 8 (t / 4) + 4 h + t % 4 (the row of accumulator register t):
   //   m32T[lane][w]  int8x4 words, byte e of word w = Tb[c][kap(4w + e, h)]:
   //                  B operand of both int8 stages (row and column);
@@ -104,8 +104,12 @@ struct alignas(256) DevTransform {
   //   m32Gs[k][p][lane][e]  Gb[c][kap(8k + e, h)] as two fp16 parts (p = 0:
   //                  Gb rounded to fp16, p = 1: the rest rounded to fp16): B
   //                  operands of both inverse stages.
-  int32_t m32_ok, m32_pad[3];
+  //   m32S[lane]     sig of region column c (row sum of T row c % N): the
+  //                  level-shift correction (128 - ell) sig of the row stage.
+  // m32_sig: the largest |sig_j| (bounds the corrected row sums).
+  int32_t m32_ok, m32_sig, m32_pad[2];
   int32_t m32T[64][4];
+  int32_t m32S[64];
   float m32W[16][64];
   int16_t m32R[16][64];
   _Float16 m32Gs[2][2][64][8];
@@ -202,7 +206,7 @@ struct MsArgs {
 constexpr int kMsTileW = 64, kMsTileH = 32;
 rklt_status launch_mssim(const MsArgs& a, int grid, void* stream);
 
-// The N in {16, 32} matrix-core kernel codes 32 x 32 pixel regions: its
+// The region matrix-core kernel codes 32 x 32 pixel regions: its
 // block index space is the grid of regions, ceil(H / 32) rows of
 // ceil(W / 32) (regions past the image edge are partly out of range).
 inline void mfma32_regions(DevImage& d) {

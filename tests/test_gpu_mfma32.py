@@ -1,6 +1,6 @@
-"""GPU parity of the N in {16, 32} matrix-core kernel (32 x 32 regions:
-one N = 32 block or 2 x 2 N = 16 blocks) against the oracle, through the
-C ABI.
+"""GPU parity of the region matrix-core kernel (32 x 32 regions of
+(32 / N)^2 blocks, N in {4, 8, 16, 32}, any level shift within its bounds)
+against the oracle, through the C ABI.
 
 Bars: the forward transform is exact int32 inside the kernel and the inverse
 FP32, so reconstructed pixels are at most 1 LSB from the oracle's
@@ -21,7 +21,7 @@ from paper_2111_14239_amd.inputs import ar1_image, random_image
 
 pytestmark = pytest.mark.gpu
 
-TIE_BAND = {16: 5e-3, 32: 1e-2}
+TIE_BAND = {4: 2e-3, 8: 2e-3, 16: 5e-3, 32: 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -92,6 +92,33 @@ def test_region_kernel_matches_oracle(ctx, N, rho):
             check(img, N, rho, alpha, r, rec, got)
 
 
+@pytest.mark.parametrize("N", [4, 8, 16, 32])
+def test_region_kernel_level_shifts(ctx, N):
+    # any level shift (N = 8 with ell = 128 stays on the N = 8 matrix-core
+    # kernel); region rows and columns cut by the image edge (N < 32)
+    rho = 0.9
+    alpha = alpha8(N, rho) if N != 8 else 2.0
+    tid = ctx.transform_id(N, rho, alpha)
+    H = 40 if N <= 8 else (48 if N == 16 else 64)
+    W = 200 if N <= 8 else (208 if N == 16 else 96)
+    img = ar1_image(H, W, rho, seed=60 + N)
+    ells = [0, 37, 255] + ([128] if N != 8 else [])
+    rs = [1, max(1, N * N // 4), N * N]
+    cases = [(r, e) for r in rs for e in ells]
+    recs, out, per = run_plan(ctx, [img] * len(cases), [tid] * len(cases), [r for r, _ in cases],
+                              [e for _, e in cases])
+    # the kernel takes a level shift while 128 L1 + |128 - ell| max|sig| <=
+    # 32640 (its row sums split into two signed bytes); the rest goes to the
+    # panel kernel
+    T = o.rounded_klt(N, rho, alpha)
+    L1, msig = int(np.abs(T).sum(1).max()), int(np.abs(T.sum(1)).max())
+    fits = [128 * L1 + abs(128 - e) * msig <= 32640 for _, e in cases]
+    assert per[4] == sum(fits) and per[0] == len(cases) - sum(fits), per
+    assert N == 32 or all(fits)
+    for (r, e), rec, got in zip(cases, recs, out):
+        check(img, N, rho, alpha, r, rec, got, e)
+
+
 def test_plain_path_and_random_pixels(ctx):
     for N in (16, 32):
         tid = ctx.transform_id(N, 0.9, alpha8(N, 0.9))
@@ -106,16 +133,16 @@ def test_plain_path_and_random_pixels(ctx):
 
 
 def test_mixed_classes_in_one_plan(ctx):
-    # N = 16: level shift 128 on the region kernel, level shift 0 and a
-    # transform beyond its bounds (alpha 100: row sums of |T| beyond 255)
-    # on the panel kernel
+    # N = 16: level shifts 128 and 0 on the region kernel, a transform
+    # beyond its bounds (alpha 100: row sums of |T| beyond 255) on the panel
+    # kernel
     N = 16
     a8 = alpha8(N, 0.9)
     t8 = ctx.transform_id(N, 0.9, a8)
     tbig = ctx.transform_id(N, 0.9, 100.0)
     imgs = [ar1_image(64, 96, 0.9, seed=3), ar1_image(48, 112, 0.7, seed=4), ar1_image(32, 48, 0.9, seed=5)]
     recs, out, per = run_plan(ctx, imgs, [t8, t8, tbig], [40, 64, 40], [128, 0, 128])
-    assert per[4] == 1 and per[0] == 2, per
+    assert per[4] == 2 and per[0] == 1, per
     for (img, al, r, ell), rec, got in zip(zip(imgs, [a8, a8, 100.0], [40, 64, 40], [128, 0, 128]), recs, out):
         check(img, N, 0.9, al, r, rec, got, ell)
 
