@@ -237,7 +237,7 @@ rklt_status rklt_ctx_add_float_transform(rklt_ctx* ctx, int32_t N, const double*
  *   dequantised scaled coefficient Q_ij c_ij (FP32), then the usual inverse
  *   A' = T_hat^-1 (Q (.) c) T_hat^-T + ell in FP32 and pixel rounding.
  * The codes are exact functions of the integer B (the same FP32 steps on any
- * IEEE machine).  These images run on the panel kernel (any N, any ell);
+ * IEEE machine).
  * scaled_out receives Q_ij c_ij for every coefficient (the quantiser's
  * output before the zonal mask), coef_out the integer B.  An identical (T, Q) returns the existing id.  Errors: E_INVAL
  * (NULL argument, unknown id, a float or already quantised transform, an
@@ -330,12 +330,14 @@ rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_
  *   class 1  the N = 8 register kernel: level shift 128, |T_ij| <= 127,
  *            128 * max row L1 <= 32767 (also every plan that dumps coefficients);
  *   class 0  the panel kernel (any N, any level shift): every other rounded
- *            transform, and every quantised one;
+ *            or quantised transform;
  *   class 3  the panel kernel in FP32: float transforms;
- *   class 4  the N in {16, 32} matrix-core kernel: level shift 128,
- *            |T_ij| <= 127 and 128 * max row L1 <= 32640 (every transform of
- *            alpha = 8 / max|K| at those N), no coefficient dump.
- * Reports the number of launches per run and, in images_per_class[5] (may be
+ *   class 4  the region matrix-core kernel (32 x 32 pixel regions, any N):
+ *            the rounded transforms the classes above do not take, with
+ *            |T_ij| <= 127 and 128 L1 + |128 - ell| max_j |sum_n T_jn| <=
+ *            32640, no coefficient dump;
+ *   class 5  the region kernel for quantised entries (same bounds).
+ * Reports the number of launches per run and, in images_per_class[6] (may be
  * NULL), how many images each class codes. */
 rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* images_per_class);
 

@@ -38,8 +38,9 @@ struct PlanPart {
 
 // Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
 // 0 = panel kernel (integer T, any N, any level shift), 3 = panel kernel for
-// float transforms, 4 = matrix-core kernel for N in {16, 32}.
-constexpr int kClasses = 5;
+// float transforms, 4 = region matrix-core kernel, 5 = region kernel with
+// the quantiser.
+constexpr int kClasses = 6;
 
 struct rklt_plan {
   rklt_ctx* ctx = nullptr;
@@ -94,7 +95,7 @@ bool region_fits(const DevTransform& t, int ell) {
 
 int kernel_class(const DevTransform& t, int ell, bool dump) {
   if (t.is_float) return 3;
-  if (t.quant) return 0;
+  if (t.quant) return (!dump && region_fits(t, ell)) ? 5 : 0;
   if (block8_fits(t, ell)) return (t.m_ok && !dump) ? 2 : 1;
   if (!dump && region_fits(t, ell)) return 4;
   return 0;
@@ -653,11 +654,10 @@ rklt_status rklt_ctx_add_quantizer(rklt_ctx* ctx, int32_t transform_id, const do
     for (int j = 0; j < N; ++j) d += static_cast<int64_t>(dt.T[i * N + j]) * dt.T[i * N + j];
     s[i] = 1.0 / std::sqrt(static_cast<double>(d));
   }
-  // quantised entries run on the panel kernel only: neither N = 8 kernel
-  // (nor its exactness report) applies
+  // quantised entries run on the region kernel (class 5) or the panel
+  // kernel: neither N = 8 kernel (nor its exactness report) applies
   dt.quant = 1;
   dt.m_ok = 0;
-  dt.m32_ok = 0;
   dt.exact = 0;
   dt.den = 0;
   for (int i = 0; i < N; ++i)
@@ -711,12 +711,12 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int PB = panel_blocks(N);
     if (cls == 2) mfma8_pad_rows(a.one);
     if (panel_class(cls)) panel_pad_rows(a.one, PB, N);
-    if (cls == 4) mfma32_regions(a.one);
+    if (cls == 4 || cls == 5) mfma32_regions(a.one);
     a.one.tile0 = 0;
     a.one.slot = 0;
     a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
                         : cls == 1 ? image_tile_blocks(a.one, wg * bpt, wg)
-                        : cls == 4 ? image_tile_blocks(a.one, 16, 4)
+                        : cls >= 4 ? image_tile_blocks(a.one, 16, 4)
                                    : image_tile_blocks(a.one, 4 * PB, 4 * PB);
     a.one.ntiles = (a.one.nblocks + a.one.tile_blocks - 1) / a.one.tile_blocks;
     a.total_tiles = a.one.ntiles;
@@ -727,7 +727,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int grid = a.total_tiles;
     return cls == 2 ? launch_mfma8(a, grid, wg, stream)
            : cls == 1 ? launch_block8(a, grid, wg, stream)
-           : cls == 4 ? launch_mfma32(a, grid, stream)
+           : cls >= 4 ? launch_mfma32(a, grid, cls == 5, stream)
                       : launch_panel(N, a, grid, mode, stream);
   }
 }
@@ -757,14 +757,15 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
                        PlanPart* q, std::vector<unsigned char>& img) {
   const bool b8 = cls == 1 || cls == 2;
   // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds;
-  // N in {16, 32} matrix-core kernel: tiles of 64 regions (16 per wave)
+  // region kernel: tiles of 16 regions (4 per wave), small enough that the
+  // resident grid's equal shares of tiles balance
   const int PB = panel_blocks(N);
-  const int base = cls == 2 ? (wg / 2) * bpt : cls == 1 ? wg * bpt : cls == 4 ? 64 : 64 * PB;
-  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : cls == 4 ? 4 : 4 * PB;
+  const int base = cls == 2 ? (wg / 2) * bpt : cls == 1 ? wg * bpt : cls >= 4 ? 16 : 64 * PB;
+  const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : cls >= 4 ? 4 : 4 * PB;
   q->mode = cls == 3 ? kPanelFloat : kPanelInt8;
   int64_t total = 0;
   for (auto& d : imgs) {
-    if (cls == 4) mfma32_regions(d);
+    if (cls >= 4) mfma32_regions(d);
     if (panel_class(cls)) {
       panel_pad_rows(d, PB, N);
       if (cls == 0 && ctx->host[d.tid].max_abs > 127) q->mode = kPanelBigT;
@@ -785,6 +786,11 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
   int auto_grid = ctx->cus * (b8 ? 2048 / q->wg : 8);
   if (cls == 2) {
     const int per_cu = mfma8_resident_wgs_per_cu(q->wg);
+    if (per_cu > 0) auto_grid = ctx->cus * per_cu;
+  }
+  if (cls >= 4) {
+    // one workgroup per resident slot, each with an equal run of tiles
+    const int per_cu = mfma32_resident_wgs_per_cu();
     if (per_cu > 0) auto_grid = ctx->cus * per_cu;
   }
   q->grid = grid_req > 0 ? grid_req : auto_grid;
@@ -875,7 +881,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   p->pixels = pixels;
   p->nparts = 0;
   p->h_image.clear();
-  for (int c : {2, 4, 1, 3, 0}) {
+  for (int c : {2, 4, 5, 1, 3, 0}) {
     if (by_class[c].empty()) continue;
     st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts], p->h_image);
     if (st) return st;
@@ -1106,7 +1112,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.dump = p->dump ? 1 : 0;
     const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
                            : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
-                           : q.cls == 4 ? launch_mfma32(a, q.grid, stream)
+                           : q.cls >= 4 ? launch_mfma32(a, q.grid, q.cls == 5, stream)
                                         : launch_panel(p->N, a, q.grid, q.mode, stream);
     if (st) return st;
   }

@@ -10,6 +10,8 @@
 //   column stage   B^T = Y^T Tb^T                two v_mfma_i32_32x32x32_i8
 //                  (Y = 256 hi + lo, hi and lo signed bytes)
 //   zonal + S      B_hat = (s_i s_j) B on the first r zig-zag positions, FP32
+//                  (quantised entries: B_hat = Q c, c = round(B / Q~) as in
+//                  Appendix A, on the same positions)
 //   inverse        Z = B_hat Gb^T, A'^T = Z^T Gb^T  v_mfma_f32_32x32x16_f16
 //                  (Gb = T_hat^-1 on the block diagonal; each FP32 operand
 //                  as two fp16 parts x = hi + lo, 22 bits, and the products
@@ -96,7 +98,9 @@ __device__ __forceinline__ RegionRows region_rows(int g, int rw, int H, int W, i
   return rr;
 }
 
-template <bool PLAN>
+// QUANT: the transform entry carries the Appendix A quantiser, which takes
+// the place of the scaling of the kept coefficients.
+template <bool PLAN, bool QUANT>
 __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
   __shared__ unsigned long long red[kM32Waves];
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
@@ -104,10 +108,10 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
   int loaded = -1, loaded_r = -1;
   v4i32 Tw = {0, 0, 0, 0};
   int S = 0;  // sig of this lane's region column
-  float WM[16];
+  float WM[16], QS[16];  // scale (or 1 / Q~) of each kept coefficient, 0 otherwise; Q
   v8f16 Gh[2] = {}, Gl[2] = {};
 #pragma unroll
-  for (int t = 0; t < 16; ++t) WM[t] = 0.0f;
+  for (int t = 0; t < 16; ++t) WM[t] = QS[t] = 0.0f;
   const v16i32 zi = {};
   const v16f32 zf = {};
   const ConstInt tile_img = (ConstInt)(a.tile_img);
@@ -121,8 +125,18 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       // per-lane operands of the transform; weights of ranks >= r zeroed
       Tw = v4i32{tf->m32T[lane][0], tf->m32T[lane][1], tf->m32T[lane][2], tf->m32T[lane][3]};
       S = tf->m32S[lane];
+      if (QUANT) {
+        const int Nt = tf->N;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) WM[t] = tf->m32R[t][lane] < r ? tf->m32W[t][lane] : 0.0f;
+        for (int t = 0; t < 16; ++t) {
+          const int idx = (c % Nt) * Nt + kap(t, h) % Nt;
+          WM[t] = tf->m32R[t][lane] < r ? tf->qinv[idx] : 0.0f;
+          QS[t] = tf->qstep[idx];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) WM[t] = tf->m32R[t][lane] < r ? tf->m32W[t][lane] : 0.0f;
+      }
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         Gh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][0][lane][0]);
@@ -195,7 +209,10 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       // register t: B[c][kap(t, h)], scaled and masked
       float Bs[16];
 #pragma unroll
-      for (int t = 0; t < 16; ++t) Bs[t] = static_cast<float>(Bh[t] * 256 + Bl[t]) * WM[t];
+      for (int t = 0; t < 16; ++t) {
+        const int B = Bh[t] * 256 + Bl[t];
+        Bs[t] = QUANT ? quantise(B, WM[t], QS[t]) : static_cast<float>(B) * WM[t];
+      }
       // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
       v16f32 Z = zf, O = zf;
       // K chunk k holds registers 8k .. 8k + 7 (skipped when all of them are)
@@ -242,10 +259,24 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
 
 }  // namespace
 
-rklt_status launch_mfma32(const KArgs& a, int grid, void* stream) {
+int mfma32_resident_wgs_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rklt_mfma32_kernel<true, false>, 64 * kM32Waves, 0) !=
+      hipSuccess)
+    return 0;
+  return n;
+}
+
+rklt_status launch_mfma32(const KArgs& a, int grid, bool quant, void* stream) {
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  if (a.imgs) hipLaunchKernelGGL(rklt_mfma32_kernel<true>, dim3(grid), dim3(64 * kM32Waves), 0, st, a);
-  else hipLaunchKernelGGL(rklt_mfma32_kernel<false>, dim3(grid), dim3(64 * kM32Waves), 0, st, a);
+  const dim3 g(grid), b(64 * kM32Waves);
+  if (a.imgs) {
+    if (quant) hipLaunchKernelGGL((rklt_mfma32_kernel<true, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((rklt_mfma32_kernel<true, false>), g, b, 0, st, a);
+  } else {
+    if (quant) hipLaunchKernelGGL((rklt_mfma32_kernel<false, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((rklt_mfma32_kernel<false, false>), g, b, 0, st, a);
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RKLT_E_HIP, "rklt_mfma32_kernel: launch failed: %s", hipGetErrorString(e));
   return RKLT_OK;

@@ -112,19 +112,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Appendix A quantiser: code c = round(B / Q~), Q~ = Q / (s s^T), with
-// t = fl32(B * fl32(1 / Q~)) and round = floor(t + 1/2), evaluated exactly as
-// floor(t) + [t - floor(t) >= 1/2]; returns the dequantised coefficient of
-// T_hat A T_hat^T, Q c.  Contraction is off so that t is rounded once and
-// the decision is taken on that FP32 value, not on an FMA's exact product.
-__device__ __forceinline__ float quantise(int B, float qinv, float qstep) {
-#pragma clang fp contract(off)
-  const float t = static_cast<float>(B) * qinv;
-  const float f = floorf(t);
-  const float c = f + (t - f >= 0.5f ? 1.0f : 0.0f);
-  return c * qstep;
-}
-
 // MODE (PanelMode): integer T within int8 (v_dot4), integer T beyond int8
 // (int32 row products), or a float transform (FP32 forward from Mf).
 template <int N, bool PLAN, int MODE>

@@ -53,6 +53,19 @@ __host__ __device__ constexpr int zz_rank(int n, int i, int j) {
   return before + ((t & 1) ? i - ilo : ihi - i);
 }
 
+// Appendix A quantiser: code c = round(B / Q~), Q~ = Q / (s s^T), with
+// t = fl32(B * fl32(1 / Q~)) and round = floor(t + 1/2), evaluated exactly as
+// floor(t) + [t - floor(t) >= 1/2]; returns the dequantised coefficient of
+// T_hat A T_hat^T, Q c.  Contraction is off so that t is rounded once and
+// the decision is taken on that FP32 value, not on an FMA's exact product.
+__device__ __forceinline__ float quantise(int B, float qinv, float qstep) {
+#pragma clang fp contract(off)
+  const float t = static_cast<float>(B) * qinv;
+  const float f = floorf(t);
+  const float c = f + (t - f >= 0.5f ? 1.0f : 0.0f);
+  return c * qstep;
+}
+
 __device__ __forceinline__ int dot2(int a, int b, int acc) {
   return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), acc,
                                 false);

@@ -214,7 +214,8 @@ inline void mfma32_regions(DevImage& d) {
   d.bwp = d.bw;
   d.nblocks = ((d.H + 31) / 32) * d.bw;
 }
-rklt_status launch_mfma32(const KArgs& a, int grid, void* stream);
+rklt_status launch_mfma32(const KArgs& a, int grid, bool quant, void* stream);
+int mfma32_resident_wgs_per_cu();
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
 int panel_blocks(int N);  // blocks of one panel of the panel kernel
 constexpr int kMaxTilesPerImage = 65535;  // tile count field of the packed accumulator

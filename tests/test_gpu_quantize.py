@@ -7,7 +7,10 @@ Bars:
     codes are the same FP32 steps on both sides);
   * reconstructed pixels: at most 1 LSB from the oracle (FP64 inverse of the
     same dequantised coefficients), and only where the oracle's value lies
-    within TIE_BAND of a rounding tie (the device inverse is FP32);
+    within TIE_BAND of a rounding tie (the device inverse is FP32 on the
+    panel kernel, two-part fp16 products with FP32 sums on the region
+    kernel; images with a dump take the panel kernel, the others the region
+    kernel within its bounds);
   * SSE: exactly sum((img - recon)^2) of the returned reconstruction; PSNR
     within the tie tolerance of the oracle's.
 """
@@ -118,8 +121,9 @@ def test_limits_fine_and_coarse(ctx):
 
 
 def test_mixed_plan_and_full_size_sample(ctx):
-    # quantised and zonal images in one plan (panel and matrix-core
-    # launches), then 1024 x 1024 images checked on strips of block rows
+    # quantised and zonal images in one plan (region kernel with the
+    # quantiser and the N = 8 matrix-core kernel), then 1024 x 1024 images
+    # checked on strips of block rows
     tid = ctx.transform_id(8, 0.9, 2.0)
     Q = ramp(8, 2.0, 1.0)
     qid = ctx.add_quantizer(tid, Q)
@@ -131,7 +135,7 @@ def test_mixed_plan_and_full_size_sample(ctx):
     ds = [rklt.empty_pitched(x.shape[0], x.shape[1]) for x in xs]
     ids = [qid, tid, qid, qid]
     plan = ctx.plan([rklt.image_desc(x, i, 64 if i == qid else 15, dst=d) for x, d, i in zip(xs, ds, ids)])
-    assert plan.images_per_class[0] == 3 and plan.images_per_class[2] == 1
+    assert plan.images_per_class[5] == 3 and plan.images_per_class[2] == 1
     res = rklt.new_results(len(xs))
     plan.run(int(res.data_ptr()))
     torch.cuda.synchronize()
