@@ -312,7 +312,8 @@ def comparison_arms(ctx, src, dst, steps: int) -> dict:
         psnr = [r["psnr_db"] for r in rklt.read_results(res)]
         out[name] = {"ms_per_launch": ms, "value": pixels / (ms / 1e3) / 1e6, "unit": "Mpixel/s",
                      "hbm_frac": BYTES_PER_PIXEL * pixels / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-                     "kernel_class": ("panel_float" if plan.images_per_class[3] else
+                     "kernel_class": ("matrix_core_region_float" if plan.images_per_class[6] else
+                                      "panel_float" if plan.images_per_class[3] else
                                       "matrix_core_n8" if plan.images_per_class[2] else
                                       "matrix_core_region_quantised" if plan.images_per_class[5] else
                                       "panel" if plan.images_per_class[0] else "other"),
@@ -488,7 +489,8 @@ def main():
             "images": n, "rejected_alpha1": rejected, "pixels": pixels,
             "tiles": plan.tiles, "grid_wgs": plan.grid, "launches_per_step": plan.launches,
             "images_per_kernel_class": dict(zip(("panel", "register_n8", "matrix_core_n8", "panel_float",
-                                                 "matrix_core_region", "matrix_core_region_quantised"),
+                                                 "matrix_core_region", "matrix_core_region_quantised",
+                                                 "matrix_core_region_float"),
                                                 plan.images_per_class)),
             "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 4,
         },

@@ -216,9 +216,10 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
  * coefficients (no scaling stage), and reconstruct A' = M^-1 B M^-T + ell,
  * pixel = clip(floor(A' + 1/2), 0, 255).  M^-1 is computed on the host in
  * FP64 (for an orthonormal M it is M^T up to rounding); the device stores M
- * and M^-1 in FP32 and codes in FP32 on the panel kernel, so a pixel may
- * differ by one level from the FP64 result where that result lies within
- * about 1e-3 (N = 8) of a rounding tie.  An identical M returns the existing
+ * and M^-1 in FP32 (panel kernel, for images with a dump) and as two fp16
+ * parts (region matrix-core kernel: fp16 products, FP32 sums, 22-bit
+ * operands), so a pixel may differ by one level from the FP64 result where
+ * that result lies within about 1e-3 (N = 8) of a rounding tie.  An identical M returns the existing
  * id.  Images of a float transform take no coef_out; scaled_out receives the
  * FP32 coefficients B.  Errors: E_INVAL (NULL argument, N, an entry not
  * finite or beyond 1e6), E_SINGULAR (M singular), E_NOMEM (table full),
@@ -331,13 +332,14 @@ rklt_status rklt_plan_info(const rklt_plan* plan, int64_t* tiles, int32_t* grid_
  *            128 * max row L1 <= 32767 (also every plan that dumps coefficients);
  *   class 0  the panel kernel (any N, any level shift): every other rounded
  *            or quantised transform;
- *   class 3  the panel kernel in FP32: float transforms;
+ *   class 3  the panel kernel in FP32: float transforms with a dump;
  *   class 4  the region matrix-core kernel (32 x 32 pixel regions, any N):
  *            the rounded transforms the classes above do not take, with
  *            |T_ij| <= 127 and 128 L1 + |128 - ell| max_j |sum_n T_jn| <=
  *            32640, no coefficient dump;
- *   class 5  the region kernel for quantised entries (same bounds).
- * Reports the number of launches per run and, in images_per_class[6] (may be
+ *   class 5  the region kernel for quantised entries (same bounds);
+ *   class 6  the region kernel for float transforms (no coefficient dump).
+ * Reports the number of launches per run and, in images_per_class[7] (may be
  * NULL), how many images each class codes. */
 rklt_status rklt_plan_launches(const rklt_plan* plan, int32_t* launches, int32_t* images_per_class);
 

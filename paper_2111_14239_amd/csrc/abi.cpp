@@ -39,8 +39,8 @@ struct PlanPart {
 // Kernel classes: 2 = matrix-core N = 8 kernel, 1 = register N = 8 kernel,
 // 0 = panel kernel (integer T, any N, any level shift), 3 = panel kernel for
 // float transforms, 4 = region matrix-core kernel, 5 = region kernel with
-// the quantiser.
-constexpr int kClasses = 6;
+// the quantiser, 6 = region kernel for float transforms.
+constexpr int kClasses = 7;
 
 struct rklt_plan {
   rklt_ctx* ctx = nullptr;
@@ -94,7 +94,7 @@ bool region_fits(const DevTransform& t, int ell) {
 }
 
 int kernel_class(const DevTransform& t, int ell, bool dump) {
-  if (t.is_float) return 3;
+  if (t.is_float) return (!dump && t.m32_ok) ? 6 : 3;
   if (t.quant) return (!dump && region_fits(t, ell)) ? 5 : 0;
   if (block8_fits(t, ell)) return (t.m_ok && !dump) ? 2 : 1;
   if (!dump && region_fits(t, ell)) return 4;
@@ -612,6 +612,28 @@ rklt_status rklt_ctx_add_float_transform(rklt_ctx* ctx, int32_t N, const double*
       dt.G[i * N + j] = static_cast<float>(G[i * N + j]);
       dt.Gt[j * N + i] = dt.G[i * N + j];
     }
+  {
+    // region kernel operands (layout in DevTransform): M and M^-1 on the
+    // block diagonal as two fp16 parts, unit weights, zig-zag ranks
+    auto kap = [](int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); };
+    dt.m32_ok = 1;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int h = lane >> 5, c = lane & 31;
+      for (int tt = 0; tt < 16; ++tt) {
+        const int j = kap(tt, h);
+        const bool diag = c / N == j / N;
+        const double mv = diag ? M[(c % N) * N + j % N] : 0.0;
+        const double gv = diag ? G[(c % N) * N + j % N] : 0.0;
+        const _Float16 mhi = static_cast<_Float16>(mv), ghi = static_cast<_Float16>(gv);
+        dt.m32Ms[tt / 8][0][lane][tt % 8] = mhi;
+        dt.m32Ms[tt / 8][1][lane][tt % 8] = static_cast<_Float16>(mv - static_cast<double>(mhi));
+        dt.m32Gs[tt / 8][0][lane][tt % 8] = ghi;
+        dt.m32Gs[tt / 8][1][lane][tt % 8] = static_cast<_Float16>(gv - static_cast<double>(ghi));
+        dt.m32W[tt][lane] = 1.0f;
+        dt.m32R[tt][lane] = static_cast<int16_t>(dt.rank[(c % N) * N + j % N]);
+      }
+    }
+  }
   std::lock_guard<std::mutex> lock(ctx->mu);
   for (size_t k = 0; k < ctx->host.size(); ++k) {
     const DevTransform& o = ctx->host[k];
@@ -711,7 +733,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int PB = panel_blocks(N);
     if (cls == 2) mfma8_pad_rows(a.one);
     if (panel_class(cls)) panel_pad_rows(a.one, PB, N);
-    if (cls == 4 || cls == 5) mfma32_regions(a.one);
+    if (cls >= 4) mfma32_regions(a.one);
     a.one.tile0 = 0;
     a.one.slot = 0;
     a.one.tile_blocks = cls == 2   ? image_tile_blocks(a.one, (wg / 2) * bpt, wg / 2)
@@ -727,7 +749,7 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
     const int grid = a.total_tiles;
     return cls == 2 ? launch_mfma8(a, grid, wg, stream)
            : cls == 1 ? launch_block8(a, grid, wg, stream)
-           : cls >= 4 ? launch_mfma32(a, grid, cls == 5, stream)
+           : cls >= 4 ? launch_mfma32(a, grid, cls - 4, stream)
                       : launch_panel(N, a, grid, mode, stream);
   }
 }
@@ -790,7 +812,7 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
   }
   if (cls >= 4) {
     // one workgroup per resident slot, each with an equal run of tiles
-    const int per_cu = mfma32_resident_wgs_per_cu();
+    const int per_cu = mfma32_resident_wgs_per_cu(cls - 4);
     if (per_cu > 0) auto_grid = ctx->cus * per_cu;
   }
   q->grid = grid_req > 0 ? grid_req : auto_grid;
@@ -881,7 +903,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   p->pixels = pixels;
   p->nparts = 0;
   p->h_image.clear();
-  for (int c : {2, 4, 5, 1, 3, 0}) {
+  for (int c : {2, 4, 5, 6, 1, 3, 0}) {
     if (by_class[c].empty()) continue;
     st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts], p->h_image);
     if (st) return st;
@@ -1112,7 +1134,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.dump = p->dump ? 1 : 0;
     const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
                            : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
-                           : q.cls >= 4 ? launch_mfma32(a, q.grid, q.cls == 5, stream)
+                           : q.cls >= 4 ? launch_mfma32(a, q.grid, q.cls - 4, stream)
                                         : launch_panel(p->N, a, q.grid, q.mode, stream);
     if (st) return st;
   }

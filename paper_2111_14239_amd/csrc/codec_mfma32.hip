@@ -1,7 +1,8 @@
 // Region matrix-core kernel of the codec (§4.1, Appendix A) for block
 // lengths N in {4, 8, 16, 32} and any level shift ell, for T with |T_ij| <=
 // 127 and 128 L1 + |128 - ell| max|sig| <= 32640 (L1 the largest row sum of
-// |T|, sig_j the row sums of T).  A wave codes one 32 x 32 pixel region per
+// |T|, sig_j the row sums of T), for quantised entries of such T, and for
+// the float comparison transforms (MODE below).  A wave codes one 32 x 32 pixel region per
 // step: (32 / N)^2 blocks through the block-diagonal Tb (T on the diagonal;
 // the off-diagonal products are zero, so the blocks stay independent).
 // Every stage is a 32 x 32 x 32 product:
@@ -98,9 +99,11 @@ __device__ __forceinline__ RegionRows region_rows(int g, int rw, int H, int W, i
   return rr;
 }
 
-// QUANT: the transform entry carries the Appendix A quantiser, which takes
-// the place of the scaling of the kept coefficients.
-template <bool PLAN, bool QUANT>
+// MODE 0: rounded transforms; 1: entries with the Appendix A quantiser,
+// which takes the place of the scaling of the kept coefficients; 2: float
+// transforms (the comparison arms): the row and column stages run on fp16
+// products of (pixel - ell), exact in fp16, and two-part M, with FP32 sums.
+template <bool PLAN, int MODE>
 __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
   __shared__ unsigned long long red[kM32Waves];
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
@@ -109,7 +112,8 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
   v4i32 Tw = {0, 0, 0, 0};
   int S = 0;  // sig of this lane's region column
   float WM[16], QS[16];  // scale (or 1 / Q~) of each kept coefficient, 0 otherwise; Q
-  v8f16 Gh[2] = {}, Gl[2] = {};
+  v8f16 Gh[2] = {}, Gl[2] = {}, Mh[2] = {}, Ml[2] = {};
+  constexpr bool QUANT = MODE == 1, FLT = MODE == 2;
 #pragma unroll
   for (int t = 0; t < 16; ++t) WM[t] = QS[t] = 0.0f;
   const v16i32 zi = {};
@@ -141,6 +145,10 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       for (int k = 0; k < 2; ++k) {
         Gh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][0][lane][0]);
         Gl[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][1][lane][0]);
+        if (FLT) {
+          Mh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Ms[k][0][lane][0]);
+          Ml[k] = *reinterpret_cast<const v8f16*>(&tf->m32Ms[k][1][lane][0]);
+        }
       }
       loaded = tid;
       loaded_r = r;
@@ -150,6 +158,7 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     const int ell = __builtin_amdgcn_readfirstlane(im->ell);
     const int lift = (128 - ell) * S;  // row-sum correction of this lane's column
     const float out_bias = static_cast<float>(ell) + 0.5f;
+    const float fell = static_cast<float>(ell);
     uint32_t keep = 0;
 #pragma unroll
     for (int t = 0; t < 16; ++t)
@@ -180,38 +189,73 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       nrr = region_rows(g + kM32Waves, rw, H, W, ps, pd, c, h, g + kM32Waves < g1);
 #pragma unroll
       for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
-      // row stage on pixel - 128 (xor 0x80 makes the bytes signed)
-      const v4i32 X = {static_cast<int>(x[0] ^ 0x80808080u), static_cast<int>(x[1] ^ 0x80808080u),
-                       static_cast<int>(x[2] ^ 0x80808080u), static_cast<int>(x[3] ^ 0x80808080u)};
-      v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
-      if (ell != 128) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) Y[t] += lift;
-      }
-      // column stage on the signed bytes of Y
-      v4i32 lo, hi;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        uint32_t wl = 0, wh = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int y = Y[4 * w + b];
-          const int l8 = static_cast<int>(static_cast<int8_t>(y & 0xff));
-          const int h8 = (y - l8) >> 8;
-          wl |= (static_cast<uint32_t>(l8) & 0xffu) << (8 * b);
-          wh |= (static_cast<uint32_t>(h8) & 0xffu) << (8 * b);
-        }
-        lo[w] = static_cast<int>(wl);
-        hi[w] = static_cast<int>(wh);
-      }
-      const v16i32 Bl = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, Tw, zi, 0, 0, 0);
-      const v16i32 Bh = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, Tw, zi, 0, 0, 0);
-      // register t: B[c][kap(t, h)], scaled and masked
       float Bs[16];
+      if constexpr (FLT) {
+        // row stage: K chunk k of lane l is pixel words x[2k], x[2k + 1]
+        // (columns kap(8k .. 8k + 7, h)), as fp16 pixel - ell
+        v16f32 Yf = zf;
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const int B = Bh[t] * 256 + Bl[t];
-        Bs[t] = QUANT ? quantise(B, WM[t], QS[t]) : static_cast<float>(B) * WM[t];
+        for (int k = 0; k < 2; ++k) {
+          v4u32 w;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const uint32_t xw = x[2 * k + p / 2];
+            const float v0 = static_cast<float>((xw >> (16 * (p % 2))) & 0xffu) - fell;
+            const float v1 = static_cast<float>((xw >> (16 * (p % 2) + 8)) & 0xffu) - fell;
+            w[p] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(v0, v1));  // exact
+          }
+          const v8f16 A = __builtin_bit_cast(v8f16, w);
+          Yf = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Mh[k], Yf, 0, 0, 0);
+          Yf = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Ml[k], Yf, 0, 0, 0);
+        }
+        // column stage on two fp16 parts of Y
+        float Yr[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Yr[t] = Yf[t];
+        v16f32 Bf = zf;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          v8f16 ah, al;
+          split_parts(&Yr[8 * k], ah, al);
+          Bf = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Mh[k], Bf, 0, 0, 0);
+          Bf = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Ml[k], Bf, 0, 0, 0);
+          Bf = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Mh[k], Bf, 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Bs[t] = Bf[t] * WM[t];
+      } else {
+        // row stage on pixel - 128 (xor 0x80 makes the bytes signed)
+        const v4i32 X = {static_cast<int>(x[0] ^ 0x80808080u), static_cast<int>(x[1] ^ 0x80808080u),
+                         static_cast<int>(x[2] ^ 0x80808080u), static_cast<int>(x[3] ^ 0x80808080u)};
+        v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
+        if (ell != 128) {
+#pragma unroll
+          for (int t = 0; t < 16; ++t) Y[t] += lift;
+        }
+        // column stage on the signed bytes of Y
+        v4i32 lo, hi;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          uint32_t wl = 0, wh = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int y = Y[4 * w + b];
+            const int l8 = static_cast<int>(static_cast<int8_t>(y & 0xff));
+            const int h8 = (y - l8) >> 8;
+            wl |= (static_cast<uint32_t>(l8) & 0xffu) << (8 * b);
+            wh |= (static_cast<uint32_t>(h8) & 0xffu) << (8 * b);
+          }
+          lo[w] = static_cast<int>(wl);
+          hi[w] = static_cast<int>(wh);
+        }
+        const v16i32 Bl = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, Tw, zi, 0, 0, 0);
+        const v16i32 Bh = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, Tw, zi, 0, 0, 0);
+        // register t: B[c][kap(t, h)], scaled and masked
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const int B = Bh[t] * 256 + Bl[t];
+          Bs[t] = QUANT ? quantise(B, WM[t], QS[t]) : static_cast<float>(B) * WM[t];
+        }
       }
       // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
       v16f32 Z = zf, O = zf;
@@ -259,23 +303,26 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
 
 }  // namespace
 
-int mfma32_resident_wgs_per_cu() {
+int mfma32_resident_wgs_per_cu(int mode) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rklt_mfma32_kernel<true, false>, 64 * kM32Waves, 0) !=
-      hipSuccess)
-    return 0;
-  return n;
+  const hipError_t e =
+      mode == 1   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rklt_mfma32_kernel<true, 1>, 64 * kM32Waves, 0)
+      : mode == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rklt_mfma32_kernel<true, 2>, 64 * kM32Waves, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rklt_mfma32_kernel<true, 0>, 64 * kM32Waves, 0);
+  return e == hipSuccess ? n : 0;
 }
 
-rklt_status launch_mfma32(const KArgs& a, int grid, bool quant, void* stream) {
+rklt_status launch_mfma32(const KArgs& a, int grid, int mode, void* stream) {
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const dim3 g(grid), b(64 * kM32Waves);
   if (a.imgs) {
-    if (quant) hipLaunchKernelGGL((rklt_mfma32_kernel<true, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((rklt_mfma32_kernel<true, false>), g, b, 0, st, a);
+    if (mode == 1) hipLaunchKernelGGL((rklt_mfma32_kernel<true, 1>), g, b, 0, st, a);
+    else if (mode == 2) hipLaunchKernelGGL((rklt_mfma32_kernel<true, 2>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((rklt_mfma32_kernel<true, 0>), g, b, 0, st, a);
   } else {
-    if (quant) hipLaunchKernelGGL((rklt_mfma32_kernel<false, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((rklt_mfma32_kernel<false, false>), g, b, 0, st, a);
+    if (mode == 1) hipLaunchKernelGGL((rklt_mfma32_kernel<false, 1>), g, b, 0, st, a);
+    else if (mode == 2) hipLaunchKernelGGL((rklt_mfma32_kernel<false, 2>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((rklt_mfma32_kernel<false, 0>), g, b, 0, st, a);
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(RKLT_E_HIP, "rklt_mfma32_kernel: launch failed: %s", hipGetErrorString(e));

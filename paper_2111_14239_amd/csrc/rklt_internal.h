@@ -107,12 +107,16 @@ struct alignas(256) DevTransform {
   //   m32S[lane]     sig of region column c (row sum of T row c % N): the
   //                  level-shift correction (128 - ell) sig of the row stage.
   // m32_sig: the largest |sig_j| (bounds the corrected row sums).
+  //   m32Ms[k][p][lane][e]  float transforms: Mb[c][kap(8k + e, h)] (M on
+  //                  the block diagonal) as two fp16 parts: B operands of the
+  //                  row and column stages.
   int32_t m32_ok, m32_sig, m32_pad[2];
   int32_t m32T[64][4];
   int32_t m32S[64];
   float m32W[16][64];
   int16_t m32R[16][64];
   _Float16 m32Gs[2][2][64][8];
+  _Float16 m32Ms[2][2][64][8];
 };
 
 // One image of a launch (device memory for a plan, a kernel argument for the
@@ -214,8 +218,9 @@ inline void mfma32_regions(DevImage& d) {
   d.bwp = d.bw;
   d.nblocks = ((d.H + 31) / 32) * d.bw;
 }
-rklt_status launch_mfma32(const KArgs& a, int grid, bool quant, void* stream);
-int mfma32_resident_wgs_per_cu();
+// mode: 0 rounded transforms, 1 quantised entries, 2 float transforms
+rklt_status launch_mfma32(const KArgs& a, int grid, int mode, void* stream);
+int mfma32_resident_wgs_per_cu(int mode);
 rklt_status launch_copy(const void* src, void* dst, size_t nbytes, void* stream);
 int panel_blocks(int N);  // blocks of one panel of the panel kernel
 constexpr int kMaxTilesPerImage = 65535;  // tile count field of the packed accumulator

@@ -99,7 +99,7 @@ def _load():
         "rklt_plan_destroy": (st, [vp]),
         "rklt_plan_info": (st, [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_copy_bytes": (st, [vp, vp, C.c_size_t, vp]),
-        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 6)]),
+        "rklt_plan_launches": (st, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32 * 7)]),
         "rklt_plan_update": (st, [vp, C.POINTER(Image), C.c_int32, vp]),
         "rklt_ctx_transform_exact": (st, [vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
         "rklt_ctx_mfma_form": (st, [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
@@ -413,11 +413,12 @@ class Plan:
         tiles, grid, pixels = C.c_int64(), C.c_int32(), C.c_int64()
         _check(_lib.rklt_plan_info(h, C.byref(tiles), C.byref(grid), C.byref(pixels)))
         self.tiles, self.grid, self.pixels = int(tiles.value), int(grid.value), int(pixels.value)
-        nl, per = C.c_int32(), (C.c_int32 * 6)()
+        nl, per = C.c_int32(), (C.c_int32 * 7)()
         _check(_lib.rklt_plan_launches(h, C.byref(nl), per))
         self.launches = int(nl.value)
         # [panel, register N=8, matrix-core N=8, panel with a float transform,
-        #  region matrix-core, region matrix-core with the quantiser]
+        #  region matrix-core, region matrix-core with the quantiser,
+        #  region matrix-core with a float transform]
         self.images_per_class = [int(v) for v in per]
         self.block8_images = self.images_per_class[1] + self.images_per_class[2]
 

@@ -362,7 +362,7 @@ def test_plan_kernel_classes(ctx):
     specs = [(64, 64, rho, a, r, 30 + k, 128) for k, (rho, a) in enumerate(N8_CASES + [(0.1, 3.0)])
              for r in (10, 57)]
     xs, dsts, plan, res = _batch(ctx, specs)
-    assert plan.launches == 1 and plan.images_per_class == [0, 0, len(specs), 0, 0, 0]
+    assert plan.launches == 1 and plan.images_per_class == [0, 0, len(specs), 0, 0, 0, 0]
     plan.run(int(res.data_ptr()))
     torch.cuda.synchronize()
     for (img, x), d, g, spec in zip(xs, dsts, rklt.read_results(res), specs):

@@ -1,7 +1,9 @@
 """GPU parity of the float comparison transforms (§4.1, Table 3: the exact
 KLT K_rho and the DCT) against the oracle, through the C ABI.
 
-Bars (the device codes in FP32, the oracle in FP64):
+Bars (the device codes in FP32 on the panel kernel, which takes images with a
+coefficient dump, and with two-part fp16 operands and FP32 sums on the region
+matrix-core kernel, which takes the others; the oracle in FP64):
   * FP32 coefficients B (scaled_out dump): |gpu - oracle| <= BTOL[N], a bound
     of FP32 accumulation over N terms twice, 128 N^2 2^-22;
   * reconstructed pixels: at most 1 LSB from the oracle, and only where the
@@ -98,13 +100,15 @@ def check(img, M, r, ell, got, N):
 KINDS = ["dct", "k0.3", "k0.4", "k0.7", "k0.8"]
 
 
+@pytest.mark.parametrize("dump", [True, False])
 @pytest.mark.parametrize("kind", KINDS)
 @pytest.mark.parametrize("r", [1, 15, 40, 64])
-def test_n8_arms_of_table3(ctx, kind, r):
-    # the paper's comparison arms at N = 8; several panels, a ragged panel tail
+def test_n8_arms_of_table3(ctx, kind, r, dump):
+    # the paper's comparison arms at N = 8 on both kernels (panel with the
+    # dump, region without); several panels and regions, ragged tails
     img = ar1_image(88, 424, 0.9, seed=r)
     tid = gpu_id(ctx, kind, 8)
-    check(img, oracle_matrix(kind, 8), r, 128, run_plain(ctx, img, tid, r, 128), 8)
+    check(img, oracle_matrix(kind, 8), r, 128, run_plain(ctx, img, tid, r, 128, dump=dump), 8)
 
 
 @pytest.mark.parametrize("N", [4, 16, 32])
@@ -118,20 +122,21 @@ def test_other_block_sizes(ctx, N, kind):
             check(img, M, r, ell, run_plain(ctx, img, tid, r, ell, dump=(r == N * N // 4)), N)
 
 
-def test_full_retention_and_constant_images(ctx):
+@pytest.mark.parametrize("dump", [True, False])
+def test_full_retention_and_constant_images(ctx, dump):
     tid = gpu_id(ctx, "dct", 8)
     img = random_image(64, 192, seed=3)
-    got = run_plain(ctx, img, tid, 64, 128)
+    got = run_plain(ctx, img, tid, 64, 128, dump=dump)
     assert np.array_equal(got["recon"], img) and got["sse"] == 0 and math.isinf(got["psnr_db"])
     for c in (0, 17, 128, 255):
         flat = np.full((32, 136), c, dtype=np.uint8)
-        got = run_plain(ctx, flat, tid, 1, 128)
+        got = run_plain(ctx, flat, tid, 1, 128, dump=dump)
         assert np.array_equal(got["recon"], flat) and got["sse"] == 0
 
 
 def test_mixed_plan_with_rounded_and_float_transforms(ctx):
-    # one plan: matrix-core (rounded, ell 128), panel (rounded, ell 0) and
-    # float images (DCT, K_0.8), all N = 8
+    # one plan: N = 8 matrix-core (rounded, ell 128), region kernel (rounded,
+    # ell 0, and the float images: DCT, K_0.8, K_0.3)
     specs = [("rklt", 0.9, 2.0, 15, 128), ("dct", None, None, 15, 128), ("k0.8", None, None, 10, 0),
              ("rklt", 0.5, 3.0, 6, 0), ("dct", None, None, 1, 77), ("k0.3", None, None, 64, 128)]
     imgs, xs, dsts, descs = [], [], [], []
@@ -145,7 +150,7 @@ def test_mixed_plan_with_rounded_and_float_transforms(ctx):
         dsts.append(d)
         descs.append(rklt.image_desc(x, tid, r, dst=d, level_shift=ell))
     plan = ctx.plan(descs)
-    assert plan.images_per_class[3] == 4 and plan.launches >= 3
+    assert plan.images_per_class[6] == 4 and plan.launches >= 3
     res = rklt.new_results(len(specs))
     ms = torch.zeros(len(specs), dtype=torch.float64, device="cuda")
     plan.run(int(res.data_ptr()))
