@@ -86,8 +86,10 @@ bool block8_fits(const DevTransform& t, int ell) {
 }
 
 // The region kernel splits the corrected row sums Y = (A - 128) T^T +
-// (128 - ell) sig into two signed bytes: |Y| <= 128 L1 + |128 - ell| max|sig|
-// must stay within 32640.
+// (128 - ell) sig into two signed bytes, hi = byte 1 of Y + 128: Y must lie
+// in [-32640, 32639].  Pixels - 128 lie in [-128, 127], so -128 L1 - c <= Y
+// <= 127 L1 + c with c = |128 - ell| max|sig|, and 128 L1 + c <= 32640
+// keeps both ends inside (L1 >= 1).
 bool region_fits(const DevTransform& t, int ell) {
   const int lift = 128 - ell;
   return t.m32_ok && 128 * t.max_row_l1 + (lift < 0 ? -lift : lift) * t.m32_sig <= 32640;

@@ -30,9 +30,12 @@
 // kap(e, h), and the tables m32T, m32Gs of the transform record hold Tb
 // and Gb in that order (an fp16 operand lane holds 8 K elements: chunk k of
 // a product takes registers 8k .. 8k + 7).  Lane l loads row c of the region at the pixel columns
-// kap(0..15, h) (four 32-bit words at columns 8q + 4h), and the last product
-// returns exactly those pixels of the reconstruction to it, so the store and
-// the squared error need no exchange.
+// kap(0..15, h) (the words at columns 8q + 4h), and the last product returns
+// exactly those pixels of the reconstruction to it, so the squared error
+// needs no exchange.  Memory is accessed 16 contiguous bytes per lane
+// (columns 16h .. 16h + 15): lanes l and l ^ 32 swap two words after the load
+// and before the store (narrow accesses scattered over 32 rows cost more
+// than the exchange).
 //
 // Truncation: register t of the inverse operands carries columns (then rows)
 // kap(t, 0) and kap(t, 1); when both are >= D modulo N (D anti-diagonals
@@ -55,19 +58,40 @@ typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 typedef _Float16 v8f16 __attribute__((ext_vector_type(8)));
 
 // Eight FP32 values as two fp16 parts: hi = x rounded toward zero, lo = the
-// (exact) remainder x - hi rounded toward zero; hi + lo carries 22 bits.
+// remainder x - hi (exact inside a mixed-precision FMA) rounded to fp16;
+// hi + lo carries 22 bits.  The trailing s_nop keeps two wait states between
+// these VALU writes and a matrix instruction that reads them.
 __device__ __forceinline__ void split_parts(const float* x, v8f16& hi, v8f16& lo) {
   v4u32 wh, wl;
 #pragma unroll
-  for (int p = 0; p < 4; ++p) {
-    const auto h2 = __builtin_amdgcn_cvt_pkrtz(x[2 * p], x[2 * p + 1]);
-    const float r0 = x[2 * p] - static_cast<float>(h2[0]);
-    const float r1 = x[2 * p + 1] - static_cast<float>(h2[1]);
-    wh[p] = __builtin_bit_cast(uint32_t, h2);
-    wl[p] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(r0, r1));
-  }
+  for (int p = 0; p < 4; ++p) wh[p] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(x[2 * p], x[2 * p + 1]));
+  uint32_t l0, l1, l2, l3;
+  asm("v_fma_mixlo_f16 %0, %4, -1.0, %8 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, %4, -1.0, %9 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixlo_f16 %1, %5, -1.0, %10 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %1, %5, -1.0, %11 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixlo_f16 %2, %6, -1.0, %12 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %2, %6, -1.0, %13 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixlo_f16 %3, %7, -1.0, %14 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %3, %7, -1.0, %15 op_sel:[1,0,0] op_sel_hi:[1,0,0]\n\t"
+      "s_nop 1"
+      : "=&v"(l0), "=&v"(l1), "=&v"(l2), "=&v"(l3)
+      : "v"(wh[0]), "v"(wh[1]), "v"(wh[2]), "v"(wh[3]), "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]),
+        "v"(x[5]), "v"(x[6]), "v"(x[7]));
+  wl[0] = l0;
+  wl[1] = l1;
+  wl[2] = l2;
+  wl[3] = l3;
   hi = __builtin_bit_cast(v8f16, wh);
   lo = __builtin_bit_cast(v8f16, wl);
+}
+
+// Byte b of a, c, e, g (in that order) as one word: two v_perm_b32 put the
+// bytes of (a, c) and (e, g) in place, a third merges them.
+__device__ __forceinline__ uint32_t gather_byte(uint32_t a, uint32_t c, uint32_t e, uint32_t g, uint32_t b) {
+  const uint32_t lo2 = __builtin_amdgcn_perm(c, a, 0x0c0c0400u | (b * 0x0101u));          // [a.b, c.b, 0, 0]
+  const uint32_t hi2 = __builtin_amdgcn_perm(g, e, 0x04000c0cu | (b * 0x01010000u));      // [0, 0, e.b, g.b]
+  return __builtin_amdgcn_perm(hi2, lo2, 0x07060100u);
 }
 
 // Waves per workgroup; they take consecutive regions.
@@ -78,25 +102,42 @@ constexpr int kRegionFlags = 0x00020000;
 
 __host__ __device__ constexpr int kap(int t, int h) { return 8 * (t >> 2) + 4 * h + (t & 3); }
 
-// Pixel words of row c of region (ry, rx): columns 8q + 4h .. + 3.
+// Row c of region (ry, rx): lane h = l / 32 loads and stores the 16 bytes at
+// columns 16h .. 16h + 15, as one 16-byte access when they all lie in the
+// image, else word by word; the accumulator layout has the words at columns
+// 8q + 4h .. + 3 (q = 0..3), which lanes l and l ^ 32 swap into place.
 struct RegionRows {
-  uint32_t os[4], od[4];
-  bool ok[4];
+  int row, col16;  // image row of this lane, first column of its 16 bytes
+  bool row_ok;     // the row lies in the image (and the region in the tile)
+  __device__ bool wide(int W) const { return row_ok && col16 + 16 <= W; }
+  // byte offset of column col16 + d at pitch p, out of range outside the image
+  __device__ uint32_t at(int d, int p, int W) const {
+    return row_ok && col16 + d < W ? static_cast<uint32_t>(row) * p + col16 + d : kRegionOut;
+  }
+  // word q of the accumulator layout (columns col16 - 16h + 8q + 4h ..) lies in the image
+  __device__ bool ok(int q, int h, int W) const { return row_ok && col16 - 12 * h + 8 * q < W; }
 };
 
-__device__ __forceinline__ RegionRows region_rows(int g, int rw, int H, int W, int ps, int pd, int c, int h,
-                                                  bool in_tile) {
+__device__ __forceinline__ RegionRows region_rows(int ry, int rx, int H, int c, int h, bool in_tile) {
   RegionRows rr;
-  const int ry = g / rw, rx = g - ry * rw;
-  const int row = ry * 32 + c;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int col = rx * 32 + 8 * q + 4 * h;
-    rr.ok[q] = in_tile && row < H && col < W;  // W is a multiple of 4: a word is all in or all out
-    rr.os[q] = rr.ok[q] ? static_cast<uint32_t>(row) * ps + col : kRegionOut;
-    rr.od[q] = rr.ok[q] ? static_cast<uint32_t>(row) * pd + col : kRegionOut;
-  }
+  rr.row = ry * 32 + c;
+  rr.col16 = rx * 32 + 16 * h;
+  rr.row_ok = in_tile && rr.row < H;
   return rr;
+}
+
+// The 16 bytes of a lane's row segment (W is a multiple of 4: each word is
+// all in or all out of the image).
+__device__ __forceinline__ void load_segment(__amdgpu_buffer_rsrc_t rs, const RegionRows& rr, int ps, int W,
+                                             uint32_t (&w)[4]) {
+  if (rr.wide(W)) {
+    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, rr.at(0, ps, W), 0, 0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = v[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, rr.at(4 * q, ps, W), 0, 0);
+  }
 }
 
 // MODE 0: rounded transforms; 1: entries with the Appendix A quantiser,
@@ -156,7 +197,8 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     const int N = __builtin_amdgcn_readfirstlane(as_constant(tf)->N);
     const int D = __builtin_amdgcn_readfirstlane(im->D);
     const int ell = __builtin_amdgcn_readfirstlane(im->ell);
-    const int lift = (128 - ell) * S;  // row-sum correction of this lane's column
+    // row-sum correction of this lane's column, plus the 128 of the byte split
+    const int lift128 = (128 - ell) * S + 128;
     const float out_bias = static_cast<float>(ell) + 0.5f;
     const float fell = static_cast<float>(ell);
     uint32_t keep = 0;
@@ -177,18 +219,36 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     const int g1 = g0 + tb < nreg ? g0 + tb : nreg;
     uint32_t sxx = 0, sxy = 0;
     // the next region's pixels are loaded while the current one is coded
-    RegionRows nrr = region_rows(g0 + wave, rw, H, W, ps, pd, c, h, g0 + wave < g1);
+    // region (ny, nxr) of index g0 + wave, then advanced by the wave stride
+    // without a division per region
+    int ny = (g0 + wave) / rw, nxr = (g0 + wave) - ((g0 + wave) / rw) * rw;
+    auto advance = [&]() {
+      nxr += kM32Waves;
+      while (nxr >= rw) {
+        nxr -= rw;
+        ++ny;
+      }
+    };
+    RegionRows nrr = region_rows(ny, nxr, H, c, h, g0 + wave < g1);
     uint32_t nx[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
+    load_segment(rs, nrr, ps, W, nx);
     for (int g = g0 + wave; g < g1; g += kM32Waves) {
       const RegionRows cur = nrr;
+      // this lane's words in the accumulator layout: h = 0 keeps columns
+      // 0-3 and 8-11 and takes 16-19 and 24-27 from its partner; h = 1 takes
+      // 4-7 and 12-15 and keeps 20-23 and 28-31
       uint32_t x[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) x[q] = nx[q];
-      nrr = region_rows(g + kM32Waves, rw, H, W, ps, pd, c, h, g + kM32Waves < g1);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) nx[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, nrr.os[q], 0, 0);
+      {
+        const uint32_t r0 = __shfl_xor(h ? nx[0] : nx[1], 32, 64);
+        const uint32_t r1 = __shfl_xor(h ? nx[2] : nx[3], 32, 64);
+        x[0] = h ? r0 : nx[0];
+        x[1] = h ? r1 : nx[2];
+        x[2] = h ? nx[1] : r0;
+        x[3] = h ? nx[3] : r1;
+      }
+      advance();
+      nrr = region_rows(ny, nxr, H, c, h, g + kM32Waves < g1);
+      load_segment(rs, nrr, ps, W, nx);
       float Bs[16];
       if constexpr (FLT) {
         // row stage: K chunk k of lane l is pixel words x[2k], x[2k + 1]
@@ -228,25 +288,17 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
         const v4i32 X = {static_cast<int>(x[0] ^ 0x80808080u), static_cast<int>(x[1] ^ 0x80808080u),
                          static_cast<int>(x[2] ^ 0x80808080u), static_cast<int>(x[3] ^ 0x80808080u)};
         v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
-        if (ell != 128) {
-#pragma unroll
-          for (int t = 0; t < 16; ++t) Y[t] += lift;
-        }
-        // column stage on the signed bytes of Y
+        // column stage on the signed bytes of Y = 256 hi + lo: with
+        // Y' = Y + 128 (plus the level-shift correction), lo is byte 0 of Y'
+        // xor 0x80 and hi is byte 1 of Y'
         v4i32 lo, hi;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          uint32_t wl = 0, wh = 0;
+        for (int t = 0; t < 16; ++t) Y[t] += lift128;
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int y = Y[4 * w + b];
-            const int l8 = static_cast<int>(static_cast<int8_t>(y & 0xff));
-            const int h8 = (y - l8) >> 8;
-            wl |= (static_cast<uint32_t>(l8) & 0xffu) << (8 * b);
-            wh |= (static_cast<uint32_t>(h8) & 0xffu) << (8 * b);
-          }
-          lo[w] = static_cast<int>(wl);
-          hi[w] = static_cast<int>(wh);
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t a = Y[4 * w], c2 = Y[4 * w + 1], e = Y[4 * w + 2], g2 = Y[4 * w + 3];
+          lo[w] = static_cast<int>(gather_byte(a, c2, e, g2, 0) ^ 0x80808080u);
+          hi[w] = static_cast<int>(gather_byte(a, c2, e, g2, 1));
         }
         const v16i32 Bl = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, Tw, zi, 0, 0, 0);
         const v16i32 Bh = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, Tw, zi, 0, 0, 0);
@@ -282,18 +334,35 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
           O = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Gh[k], O, 0, 0, 0);
         }
       // register t of O: A'[c][kap(t, h)] - ell
+      uint32_t o[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         uint32_t word = 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v] + out_bias), v, word);
-        __builtin_amdgcn_raw_buffer_store_b32(word, rd, cur.od[q], 0, 0);
-        if (cur.ok[q]) {
+        o[q] = word;
+        if (cur.ok(q, h, W)) {
           sxx = __builtin_amdgcn_udot4(x[q], x[q], sxx, false);
           sxx = __builtin_amdgcn_udot4(word, word, sxx, false);
           sxy = __builtin_amdgcn_udot4(x[q], word, sxy, false);
         }
+      }
+      // columns 16h .. 16h + 15 of row c: lane h = 0 holds 0-3 and 8-11 and
+      // needs 4-7 and 12-15 from its partner (which holds them in its
+      // words 0 and 1), lane h = 1 the converse with 16-19 and 24-27
+      const uint32_t r0 = __shfl_xor(h ? o[0] : o[2], 32, 64);
+      const uint32_t r1 = __shfl_xor(h ? o[1] : o[3], 32, 64);
+      v4u32 w;
+      w[0] = h ? r0 : o[0];
+      w[1] = h ? o[2] : r0;
+      w[2] = h ? r1 : o[1];
+      w[3] = h ? o[3] : r1;
+      if (cur.wide(W)) {
+        __builtin_amdgcn_raw_buffer_store_b128(w, rd, cur.at(0, pd, W), 0, 0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) __builtin_amdgcn_raw_buffer_store_b32(w[q], rd, cur.at(4 * q, pd, W), 0, 0);
       }
     }
     reduce_and_finish(static_cast<unsigned long long>(sxx - 2u * sxy), red, a.res + im->slot, 1, im->ntiles,
