@@ -25,7 +25,7 @@ COMMON = [
 ]
 
 
-# per-file flags: the N in {16, 32} matrix-core kernel keeps its accumulators
+# per-file flags: the region matrix-core kernel keeps its accumulators
 # in ordinary VGPRs (no accumulator-register copies; one more wave per SIMD)
 PER_FILE = {"codec_mfma32.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
