@@ -199,3 +199,58 @@ def test_precision_of_the_region_inverse(ctx, N):
         assert off / diff.size <= 2e-3
     print(f"\nN={N} region kernel: (r, share of pixels off by one, largest |x - tie| among them, |dPSNR| dB)",
           [(r, f"{s:.2e}", f"{t:.1e}", f"{p:.1e}") for r, s, t, p in stats])
+
+
+def test_region_tiles_grow_for_the_largest_images(ctx):
+    # 32768 x 32800 pixels at N = 16: 1,049,600 regions, more than 65535
+    # tiles of the default 16 regions, so the library widens this image's
+    # tiles (plain path and plan); SSE against the reconstruction (summed on
+    # the device in int64) and sampled regions against the oracle
+    N, rho = 16, 0.9
+    a = alpha8(N, rho)
+    tid = ctx.transform_id(N, rho, a)
+    H, W = 32768, 32800
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    x = torch.randint(0, 256, (H, W), dtype=torch.uint8, device="cuda", generator=gen)
+    d = torch.empty_like(x)
+    res = rklt.new_results(1)
+    ctx.codec(rklt.image_desc(x, tid, 40, dst=d), int(res.data_ptr()))
+    torch.cuda.synchronize()
+    g = rklt.read_results(res)[0]
+    assert 0 < g["tiles"] <= 65535
+    sse = int(((x.to(torch.int64) - d.to(torch.int64)) ** 2).sum().item())
+    assert g["sse"] == sse
+    rng = np.random.default_rng(2)
+    for ry, rx in rng.integers(0, [H // 32, W // 32 - 1], size=(6, 2)):
+        img = x[32 * ry:32 * ry + 32, 32 * rx:32 * rx + 32].cpu().numpy()
+        rec = d[32 * ry:32 * ry + 32, 32 * rx:32 * rx + 32].cpu().numpy()
+        ref = o.codec(img, N, rho, a, 40, 128)
+        diff = rec.astype(np.int64) - ref["recon"].astype(np.int64)
+        assert np.max(np.abs(diff)) <= 1
+        frac = ref["pre_round"] - np.floor(ref["pre_round"])
+        assert np.all((np.abs(frac - 0.5) <= TIE_BAND[N])[diff != 0])
+    # the right edge: W = 32800 leaves a half region (16 columns) per region row
+    img = x[:32, W - 48:].cpu().numpy()
+    rec = d[:32, W - 48:].cpu().numpy()
+    ref = o.codec(img, N, rho, a, 40, 128)
+    assert np.max(np.abs(rec.astype(np.int64) - ref["recon"].astype(np.int64))) <= 1
+    del x, d
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("N,ell", [(4, 0), (8, 0), (8, 200), (4, 128)])
+def test_region_plain_path_small_blocks(ctx, N, ell):
+    # one image on the plain path at N = 4 and 8 (N = 8 only with ell != 128,
+    # which the N = 8 kernels do not take), sides that cut regions
+    rho = 0.7
+    alpha = alpha8(N, rho) if N == 4 else 2.0
+    tid = ctx.transform_id(N, rho, alpha)
+    img = random_image(72, 104, seed=N + ell)
+    x = torch.from_numpy(img).cuda()
+    d = torch.empty_like(x)
+    res = rklt.new_results(1)
+    for r in (1, N * N // 2, N * N):
+        ctx.codec(rklt.image_desc(x, tid, r, dst=d, level_shift=ell), int(res.data_ptr()))
+        torch.cuda.synchronize()
+        check(img, N, rho, alpha, r, d.cpu().numpy(), rklt.read_results(res)[0], ell)
