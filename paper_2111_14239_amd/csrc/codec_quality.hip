@@ -5,11 +5,12 @@
 // image, averaged).
 //
 // rklt_ssim_tiles_kernel: a workgroup codes output tiles of 32 x 64 window
-// positions.  It stages the 42 x 74 source and reconstruction pixels the
-// tile needs in LDS (minus 128, which keeps the second moments small), runs
-// the horizontal 11-tap pass of the five quantities x, y, x^2, y^2, xy from
-// registers into LDS, then each thread runs the vertical pass for 8 positions of one column
-// in registers, evaluates SSIM and adds it up.  Each tile's sum goes to its
+// positions.  It runs the horizontal 11-tap pass of the five quantities x,
+// y, x^2, y^2, xy over the 42 x 74 source and reconstruction pixels the tile
+// needs (read from the images into registers, minus 128, which keeps the
+// second moments small) into LDS, then each thread runs the vertical pass
+// for 8 positions of one column in registers, evaluates SSIM and adds it
+// up.  Each tile's sum goes to its
 // own slot (double), and rklt_ssim_mean_kernel adds an image's slots in a
 // fixed order and divides by the number of positions, so the result does
 // not depend on scheduling.  FP32 arithmetic, double sums.
@@ -37,44 +38,52 @@ __device__ __forceinline__ float gtap(int k) {
   return expf(-static_cast<float>((k - 5) * (k - 5)) / 4.5f) / s;
 }
 
-// W horizontal-pass outputs of row r from column c0: the 11-tap weighted
-// sums of x, y, x^2, y^2 and xy; the products are formed once per pixel
+// W horizontal-pass outputs of tile row r from tile column c0: the 11-tap
+// weighted sums of x, y, x^2, y^2 and xy, one quantity after another.  The
+// W + 10 pixels of x and y are read from the images as 32-bit words (rows
+// start on 8-byte boundaries and W, x0 and c0 are multiples of 4, so each
+// word is aligned and lies wholly inside or wholly past its row; past the
+// last row the buffer reads zero); pixels outside the image only feed
+// positions that are not evaluated.  Pixels are taken minus 128, which keeps
+// the second moments below 128^2 and the FP32 cancellation in E[x^2] - mu^2
+// small.
 template <int W>
-__device__ __forceinline__ void hpass(const float (*sx)[kIW + 1], const float (*sy)[kIW + 1],
-                                      float (*sh)[kIH][kTW + 1], int r, int c0, const float* g) {
-  float vx[W + 10], vy[W + 10], vxx[W + 10], vyy[W + 10], vxy[W + 10];
+__device__ __forceinline__ void hpass(__amdgpu_buffer_rsrc_t rx, __amdgpu_buffer_rsrc_t ry, uint32_t ox,
+                                      uint32_t oy, float (*sh)[kIH][kTW + 1], int r, int c0, const float* g) {
+  constexpr int kN = W + 10, kWords = (kN + 3) / 4;
+  float vx[kN], vy[kN];
 #pragma unroll
-  for (int k = 0; k < W + 10; ++k) {
-    vx[k] = sx[r][c0 + k];
-    vy[k] = sy[r][c0 + k];
-    vxx[k] = vx[k] * vx[k];
-    vyy[k] = vy[k] * vy[k];
-    vxy[k] = vx[k] * vy[k];
+  for (int w = 0; w < kWords; ++w) {
+    const uint32_t wx = __builtin_amdgcn_raw_buffer_load_b32(rx, ox + (ox == 0x80000000u ? 0u : 4u * w), 0, 0);
+    const uint32_t wy = __builtin_amdgcn_raw_buffer_load_b32(ry, oy + (oy == 0x80000000u ? 0u : 4u * w), 0, 0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (4 * w + b < kN) {
+        vx[4 * w + b] = static_cast<float>((wx >> (8 * b)) & 0xffu) - 128.0f;
+        vy[4 * w + b] = static_cast<float>((wy >> (8 * b)) & 0xffu) - 128.0f;
+      }
+    }
   }
 #pragma unroll
-  for (int c = 0; c < W; ++c) {
-    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f, m4 = 0.0f;
+  for (int q = 0; q < 5; ++q) {
+    float v[kN];
 #pragma unroll
-    for (int k = 0; k < 11; ++k) {
-      m0 = fmaf(g[k], vx[c + k], m0);
-      m1 = fmaf(g[k], vy[c + k], m1);
-      m2 = fmaf(g[k], vxx[c + k], m2);
-      m3 = fmaf(g[k], vyy[c + k], m3);
-      m4 = fmaf(g[k], vxy[c + k], m4);
+    for (int k = 0; k < kN; ++k)
+      v[k] = q == 0 ? vx[k] : q == 1 ? vy[k] : q == 2 ? vx[k] * vx[k] : q == 3 ? vy[k] * vy[k] : vx[k] * vy[k];
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      float m = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 11; ++k) m = fmaf(g[k], v[c + k], m);
+      sh[q][r][c0 + c] = m;
     }
-    sh[0][r][c0 + c] = m0;
-    sh[1][r][c0 + c] = m1;
-    sh[2][r][c0 + c] = m2;
-    sh[3][r][c0 + c] = m3;
-    sh[4][r][c0 + c] = m4;
   }
 }
 
 __global__ __launch_bounds__(256) void rklt_ssim_tiles_kernel(MsArgs a) {
-  __shared__ float sx[kIH][kIW + 1];
-  __shared__ float sy[kIH][kIW + 1];
-  __shared__ float sh[5][kIH][kTW + 1];  // horizontal pass: mu_x, mu_y, x^2, y^2, xy
-  __shared__ double red[4];
+  // horizontal pass: mu_x, mu_y, x^2, y^2, xy (54600 bytes: three
+  // workgroups fit a CU's LDS; the workgroup sums reuse its first bytes)
+  __shared__ float sh[5][kIH][kTW + 1];
   float g[11];
 #pragma unroll
   for (int k = 0; k < 11; ++k) g[k] = gtap(k);
@@ -95,56 +104,49 @@ __global__ __launch_bounds__(256) void rklt_ssim_tiles_kernel(MsArgs a) {
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(im->x), 0, (H - 1) * im->px + W, kQuality);
     const __amdgpu_buffer_rsrc_t ry =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(im->y), 0, (H - 1) * im->py + W, kQuality);
+    auto row_offset = [&](int r, int c0, int pitch) {
+      return y0 + r < H ? static_cast<uint32_t>(y0 + r) * pitch + (x0 + c0) : 0x80000000u;
+    };
     __syncthreads();  // the previous tile's LDS reads are done
-    // stage the pixels, four per load: image rows start on 8-byte boundaries
-    // and W and x0 are multiples of 4, so each word is aligned and lies
-    // wholly inside or wholly past its row (past the last row it reads zero);
-    // pixels outside the image only feed positions that are not evaluated
-    constexpr int kWords = (kIW + 3) / 4;
-    for (int e = threadIdx.x; e < kIH * kWords; e += blockDim.x) {
-      const int r = e / kWords, w = e % kWords;
-      const bool in = y0 + r < H;
-      const uint32_t ox = in ? static_cast<uint32_t>(y0 + r) * im->px + (x0 + 4 * w) : 0x80000000u;
-      const uint32_t oy = in ? static_cast<uint32_t>(y0 + r) * im->py + (x0 + 4 * w) : 0x80000000u;
-      const uint32_t vx = __builtin_amdgcn_raw_buffer_load_b32(rx, ox, 0, 0);
-      const uint32_t vy = __builtin_amdgcn_raw_buffer_load_b32(ry, oy, 0, 0);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        if (4 * w + b < kIW) {
-          sx[r][4 * w + b] = static_cast<float>((vx >> (8 * b)) & 0xffu) - 128.0f;
-          sy[r][4 * w + b] = static_cast<float>((vy >> (8 * b)) & 0xffu) - 128.0f;
-        }
-      }
-    }
-    __syncthreads();
     // horizontal pass: rows 0 .. 31 in items of 8 outputs (256 items, one
     // per thread), the last 10 rows in items of 4 (160 items), so no wave
     // runs more than 12 outputs
-    hpass<8>(sx, sy, sh, threadIdx.x / (kTW / 8), (threadIdx.x % (kTW / 8)) * 8, g);
-    if (threadIdx.x < (kIH - 32) * (kTW / 4))
-      hpass<4>(sx, sy, sh, 32 + threadIdx.x / (kTW / 4), (threadIdx.x % (kTW / 4)) * 4, g);
+    {
+      const int r = threadIdx.x / (kTW / 8), c0 = (threadIdx.x % (kTW / 8)) * 8;
+      hpass<8>(rx, ry, row_offset(r, c0, im->px), row_offset(r, c0, im->py), sh, r, c0, g);
+    }
+    if (threadIdx.x < (kIH - 32) * (kTW / 4)) {
+      const int r = 32 + threadIdx.x / (kTW / 4), c0 = (threadIdx.x % (kTW / 4)) * 4;
+      hpass<4>(rx, ry, row_offset(r, c0, im->px), row_offset(r, c0, im->py), sh, r, c0, g);
+    }
     __syncthreads();
-    // vertical pass and SSIM: column c, rows r0 .. r0 + 7
+    // vertical pass and SSIM: column c, rows r0 .. r0 + 7, one quantity
+    // after another (m[q][i] in the same tap order as before)
     const int c = threadIdx.x % kTW, r0 = (threadIdx.x / kTW) * 8;
     const int vh = H - 10 - y0, vw = W - 10 - x0;  // valid positions in this tile
     float sum = 0.0f;
     if (c < vw) {
-      float col[5][18];
+      float m[5][8];
 #pragma unroll
-      for (int q = 0; q < 5; ++q)
+      for (int q = 0; q < 5; ++q) {
+        float col[18];
 #pragma unroll
-        for (int k = 0; k < 18; ++k) col[q][k] = sh[q][r0 + k][c];
+        for (int k = 0; k < 18; ++k) col[k] = sh[q][r0 + k][c];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int k = 0; k < 11; ++k) acc = fmaf(g[k], col[i + k], acc);
+          m[q][i] = acc;
+        }
+      }
       const float C1 = 6.5025f, C2 = 58.5225f;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        float m[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int k = 0; k < 11; ++k)
-#pragma unroll
-          for (int q = 0; q < 5; ++q) m[q] = fmaf(g[k], col[q][i + k], m[q]);
         // m[0], m[1]: means of x - 128, y - 128
-        const float mx = m[0] + 128.0f, my = m[1] + 128.0f;
-        const float vxx = m[2] - m[0] * m[0], vyy = m[3] - m[1] * m[1], cxy = m[4] - m[0] * m[1];
+        const float mx = m[0][i] + 128.0f, my = m[1][i] + 128.0f;
+        const float vxx = m[2][i] - m[0][i] * m[0][i], vyy = m[3][i] - m[1][i] * m[1][i];
+        const float cxy = m[4][i] - m[0][i] * m[1][i];
         const float num = (2.0f * mx * my + C1) * (2.0f * cxy + C2);
         const float den = (mx * mx + my * my + C1) * (vxx + vyy + C2);
         // one rounding of the reciprocal (1 ulp) instead of a correctly
@@ -157,6 +159,8 @@ __global__ __launch_bounds__(256) void rklt_ssim_tiles_kernel(MsArgs a) {
     double s = static_cast<double>(sum);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __syncthreads();  // every read of sh is done: its first bytes take the wave sums
+    double* const red = reinterpret_cast<double*>(&sh[0][0][0]);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) a.partials[t] = red[0] + red[1] + red[2] + red[3];
