@@ -2,10 +2,10 @@
 // lengths N in {4, 8, 16, 32} and any level shift ell, for T with |T_ij| <=
 // 127 and 128 L1 + |128 - ell| max|sig| <= 32640 (L1 the largest row sum of
 // |T|, sig_j the row sums of T), for quantised entries of such T, and for
-// the float comparison transforms (MODE below).  A wave codes one 32 x 32 pixel region per
-// step: (32 / N)^2 blocks through the block-diagonal Tb (T on the diagonal;
-// the off-diagonal products are zero, so the blocks stay independent).
-// Every stage is a 32 x 32 x 32 product:
+// the float comparison transforms (MODE below).  A wave codes one 32 x 32
+// pixel region per step: (32 / N)^2 blocks through the block-diagonal Tb (T
+// on the diagonal; the off-diagonal products are zero, so the blocks stay
+// independent).  Every stage is a 32 x 32 x 32 product:
 //   row stage      Y  = (A - 128) Tb^T + (128 - ell) sig   v_mfma_i32_32x32x32_i8
 //                  (the row sums of A - ell, from signed pixel bytes)
 //   column stage   B^T = Y^T Tb^T                two v_mfma_i32_32x32x32_i8
@@ -23,19 +23,19 @@
 //
 // Layouts.  With h = lane / 32 and c = lane % 32, accumulator register t of
 // lane l holds row kap(t, h) = 8 (t / 4) + 4 h + t % 4, column c; an int8
-// operand lane holds row (A) or column (B) c and 16 K elements, an FP32
-// operand lane one K element (h).  The K order of a product only has to
-// agree between its two operands, so every stage reads the previous stage's
+// operand lane holds row (A) or column (B) c and 16 K elements, an fp16
+// operand lane 8 K elements.  The K order of a product only has to agree
+// between its two operands, so every stage reads the previous stage's
 // accumulator registers as they are: K element e of lane l is index
-// kap(e, h), and the tables m32T, m32Gs of the transform record hold Tb
-// and Gb in that order (an fp16 operand lane holds 8 K elements: chunk k of
-// a product takes registers 8k .. 8k + 7).  Lane l loads row c of the region at the pixel columns
-// kap(0..15, h) (the words at columns 8q + 4h), and the last product returns
-// exactly those pixels of the reconstruction to it, so the squared error
-// needs no exchange.  Memory is accessed 16 contiguous bytes per lane
-// (columns 16h .. 16h + 15): lanes l and l ^ 32 swap two words after the load
-// and before the store (narrow accesses scattered over 32 rows cost more
-// than the exchange).
+// kap(e, h) (for fp16 operands, chunk k of a product takes registers
+// 8k .. 8k + 7), and the tables m32T, m32Gs, m32Ms of the transform record
+// hold Tb, Gb and Mb in that order.  Lane l holds row c of the region at the
+// pixel columns kap(0..15, h) (the words at columns 8q + 4h), and the last
+// product returns exactly those pixels of the reconstruction to it, so the
+// squared error needs no exchange.  Memory is accessed 16 contiguous bytes
+// per lane (columns 16h .. 16h + 15): lanes l and l ^ 32 swap two words
+// after the load and before the store (narrow accesses scattered over 32
+// rows cost more than the exchange).
 //
 // Truncation: register t of the inverse operands carries columns (then rows)
 // kap(t, 0) and kap(t, 1); when both are >= D modulo N (D anti-diagonals
