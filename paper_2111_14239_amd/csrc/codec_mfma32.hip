@@ -17,7 +17,11 @@
 //                  (Gb = T_hat^-1 on the block diagonal; each FP32 operand
 //                  as two fp16 parts x = hi + lo, 22 bits, and the products
 //                  hi hi + hi lo + lo hi accumulated in FP32)
-//   pixel          clip(floor(A' + ell + 1/2)), squared error
+//   pixel          clip(floor(A' + ell + 1/2)), squared error: one add and
+//                  the saturating round-to-nearest byte conversion of
+//                  A' + ell + 2^-12 (the nudge sends exact ties up; it
+//                  differs from floor(x + 1/2) only within 2^-12 below a
+//                  tie, inside the FP32 inverse's own tie band)
 // so B = T (A - ell) T^T is exact int32 and the inverse is FP32 up to the
 // dropped lo lo terms (relative 2^-22).
 //
@@ -34,8 +38,8 @@
 // product returns exactly those pixels of the reconstruction to it, so the
 // squared error needs no exchange.  Memory is accessed 16 contiguous bytes
 // per lane (columns 16h .. 16h + 15): lanes l and l ^ 32 swap two words
-// after the load and before the store (narrow accesses scattered over 32
-// rows cost more than the exchange).
+// after the load and before the store, one v_permlane32_swap per two words
+// (narrow accesses scattered over 32 rows cost more than the exchange).
 //
 // Truncation: register t of the inverse operands carries columns (then rows)
 // kap(t, 0) and kap(t, 1); when both are >= D modulo N (D anti-diagonals
@@ -55,6 +59,7 @@ typedef int v4i32 __attribute__((ext_vector_type(4)));
 typedef int v16i32 __attribute__((ext_vector_type(16)));
 typedef float v16f32 __attribute__((ext_vector_type(16)));
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
 typedef _Float16 v8f16 __attribute__((ext_vector_type(8)));
 
 // Eight FP32 values as two fp16 parts: hi = x rounded toward zero, lo = the
@@ -107,36 +112,44 @@ __host__ __device__ constexpr int kap(int t, int h) { return 8 * (t >> 2) + 4 * 
 // image, else word by word; the accumulator layout has the words at columns
 // 8q + 4h .. + 3 (q = 0..3), which lanes l and l ^ 32 swap into place.
 struct RegionRows {
-  int row, col16;  // image row of this lane, first column of its 16 bytes
-  bool row_ok;     // the row lies in the image (and the region in the tile)
+  int row, col16;     // image row of this lane, first column of its 16 bytes
+  uint32_t so, dof;   // byte offsets of (row, col16) in the source and destination
+  bool row_ok;        // the row lies in the image (and the region in the tile)
   __device__ bool wide(int W) const { return row_ok && col16 + 16 <= W; }
-  // byte offset of column col16 + d at pitch p, out of range outside the image
-  __device__ uint32_t at(int d, int p, int W) const {
-    return row_ok && col16 + d < W ? static_cast<uint32_t>(row) * p + col16 + d : kRegionOut;
-  }
+  // byte offset of column col16 + d, out of range outside the image
+  __device__ uint32_t src(int d, int W) const { return row_ok && col16 + d < W ? so + d : kRegionOut; }
+  __device__ uint32_t dst(int d, int W) const { return row_ok && col16 + d < W ? dof + d : kRegionOut; }
   // word q of the accumulator layout (columns col16 - 16h + 8q + 4h ..) lies in the image
   __device__ bool ok(int q, int h, int W) const { return row_ok && col16 - 12 * h + 8 * q < W; }
+  // every word of the region row lies in the image
+  __device__ bool full(int h, int W) const { return row_ok && col16 - 16 * h + 32 <= W; }
 };
 
-__device__ __forceinline__ RegionRows region_rows(int ry, int rx, int H, int c, int h, bool in_tile) {
+// bs, bd: byte offsets of the start of image row 32 ry + c in the source and
+// destination (kept up to date as the region row advances: no multiply per
+// region)
+__device__ __forceinline__ RegionRows region_rows(int ry, int rx, int H, int c, int h, bool in_tile, uint32_t bs,
+                                                  uint32_t bd) {
   RegionRows rr;
   rr.row = ry * 32 + c;
   rr.col16 = rx * 32 + 16 * h;
+  rr.so = bs + rr.col16;
+  rr.dof = bd + rr.col16;
   rr.row_ok = in_tile && rr.row < H;
   return rr;
 }
 
 // The 16 bytes of a lane's row segment (W is a multiple of 4: each word is
 // all in or all out of the image).
-__device__ __forceinline__ void load_segment(__amdgpu_buffer_rsrc_t rs, const RegionRows& rr, int ps, int W,
+__device__ __forceinline__ void load_segment(__amdgpu_buffer_rsrc_t rs, const RegionRows& rr, int W,
                                              uint32_t (&w)[4]) {
   if (rr.wide(W)) {
-    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, rr.at(0, ps, W), 0, 0);
+    const v4u32 v = __builtin_amdgcn_raw_buffer_load_b128(rs, rr.src(0, W), 0, 0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) w[q] = v[q];
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, rr.at(4 * q, ps, W), 0, 0);
+    for (int q = 0; q < 4; ++q) w[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, rr.src(4 * q, W), 0, 0);
   }
 }
 
@@ -199,7 +212,7 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     const int ell = __builtin_amdgcn_readfirstlane(im->ell);
     // row-sum correction of this lane's column, plus the 128 of the byte split
     const int lift128 = (128 - ell) * S + 128;
-    const float out_bias = static_cast<float>(ell) + 0.5f;
+    const float out_bias = static_cast<float>(ell) + 0x1p-12f;
     const float fell = static_cast<float>(ell);
     uint32_t keep = 0;
 #pragma unroll
@@ -222,33 +235,38 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     // region (ny, nxr) of index g0 + wave, then advanced by the wave stride
     // without a division per region
     int ny = (g0 + wave) / rw, nxr = (g0 + wave) - ((g0 + wave) / rw) * rw;
+    uint32_t bs = static_cast<uint32_t>(ny * 32 + c) * static_cast<uint32_t>(ps);
+    uint32_t bd = static_cast<uint32_t>(ny * 32 + c) * static_cast<uint32_t>(pd);
     auto advance = [&]() {
       nxr += kM32Waves;
       while (nxr >= rw) {
         nxr -= rw;
         ++ny;
+        bs += 32u * static_cast<uint32_t>(ps);
+        bd += 32u * static_cast<uint32_t>(pd);
       }
     };
-    RegionRows nrr = region_rows(ny, nxr, H, c, h, g0 + wave < g1);
+    RegionRows nrr = region_rows(ny, nxr, H, c, h, g0 + wave < g1, bs, bd);
     uint32_t nx[4];
-    load_segment(rs, nrr, ps, W, nx);
+    load_segment(rs, nrr, W, nx);
     for (int g = g0 + wave; g < g1; g += kM32Waves) {
       const RegionRows cur = nrr;
       // this lane's words in the accumulator layout: h = 0 keeps columns
       // 0-3 and 8-11 and takes 16-19 and 24-27 from its partner; h = 1 takes
-      // 4-7 and 12-15 and keeps 20-23 and 28-31
+      // 4-7 and 12-15 and keeps 20-23 and 28-31 (v_permlane32_swap trades
+      // lanes 32-63 of its first operand for lanes 0-31 of its second)
       uint32_t x[4];
       {
-        const uint32_t r0 = __shfl_xor(h ? nx[0] : nx[1], 32, 64);
-        const uint32_t r1 = __shfl_xor(h ? nx[2] : nx[3], 32, 64);
-        x[0] = h ? r0 : nx[0];
-        x[1] = h ? r1 : nx[2];
-        x[2] = h ? nx[1] : r0;
-        x[3] = h ? nx[3] : r1;
+        const v2u32 s01 = __builtin_amdgcn_permlane32_swap(nx[0], nx[1], false, false);
+        const v2u32 s23 = __builtin_amdgcn_permlane32_swap(nx[2], nx[3], false, false);
+        x[0] = s01[0];
+        x[1] = s23[0];
+        x[2] = s01[1];
+        x[3] = s23[1];
       }
       advance();
-      nrr = region_rows(ny, nxr, H, c, h, g + kM32Waves < g1);
-      load_segment(rs, nrr, ps, W, nx);
+      nrr = region_rows(ny, nxr, H, c, h, g + kM32Waves < g1, bs, bd);
+      load_segment(rs, nrr, W, nx);
       float Bs[16];
       if constexpr (FLT) {
         // row stage: K chunk k of lane l is pixel words x[2k], x[2k + 1]
@@ -340,29 +358,42 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
         uint32_t word = 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          word = __builtin_amdgcn_cvt_pk_u8_f32(floorf(O[4 * q + v] + out_bias), v, word);
+          word = __builtin_amdgcn_cvt_pk_u8_f32(O[4 * q + v] + out_bias, v, word);
         o[q] = word;
-        if (cur.ok(q, h, W)) {
+      }
+      // squared error over the words that lie in the image (all of them
+      // inside the image: no per-word test)
+      if (cur.full(h, W)) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
           sxx = __builtin_amdgcn_udot4(x[q], x[q], sxx, false);
-          sxx = __builtin_amdgcn_udot4(word, word, sxx, false);
-          sxy = __builtin_amdgcn_udot4(x[q], word, sxy, false);
+          sxx = __builtin_amdgcn_udot4(o[q], o[q], sxx, false);
+          sxy = __builtin_amdgcn_udot4(x[q], o[q], sxy, false);
         }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (cur.ok(q, h, W)) {
+            sxx = __builtin_amdgcn_udot4(x[q], x[q], sxx, false);
+            sxx = __builtin_amdgcn_udot4(o[q], o[q], sxx, false);
+            sxy = __builtin_amdgcn_udot4(x[q], o[q], sxy, false);
+          }
       }
       // columns 16h .. 16h + 15 of row c: lane h = 0 holds 0-3 and 8-11 and
       // needs 4-7 and 12-15 from its partner (which holds them in its
       // words 0 and 1), lane h = 1 the converse with 16-19 and 24-27
-      const uint32_t r0 = __shfl_xor(h ? o[0] : o[2], 32, 64);
-      const uint32_t r1 = __shfl_xor(h ? o[1] : o[3], 32, 64);
+      const v2u32 s02 = __builtin_amdgcn_permlane32_swap(o[0], o[2], false, false);
+      const v2u32 s13 = __builtin_amdgcn_permlane32_swap(o[1], o[3], false, false);
       v4u32 w;
-      w[0] = h ? r0 : o[0];
-      w[1] = h ? o[2] : r0;
-      w[2] = h ? r1 : o[1];
-      w[3] = h ? o[3] : r1;
+      w[0] = s02[0];
+      w[1] = s02[1];
+      w[2] = s13[0];
+      w[3] = s13[1];
       if (cur.wide(W)) {
-        __builtin_amdgcn_raw_buffer_store_b128(w, rd, cur.at(0, pd, W), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(w, rd, cur.dst(0, W), 0, 0);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) __builtin_amdgcn_raw_buffer_store_b32(w[q], rd, cur.at(4 * q, pd, W), 0, 0);
+        for (int q = 0; q < 4; ++q) __builtin_amdgcn_raw_buffer_store_b32(w[q], rd, cur.dst(4 * q, W), 0, 0);
       }
     }
     reduce_and_finish(static_cast<unsigned long long>(sxx - 2u * sxy), red, a.res + im->slot, 1, im->ntiles,
