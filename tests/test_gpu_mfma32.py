@@ -254,3 +254,26 @@ def test_region_plain_path_small_blocks(ctx, N, ell):
         ctx.codec(rklt.image_desc(x, tid, r, dst=d, level_shift=ell), int(res.data_ptr()))
         torch.cuda.synchronize()
         check(img, N, rho, alpha, r, d.cpu().numpy(), rklt.read_results(res)[0], ell)
+
+
+@pytest.mark.parametrize("ell", [128, 0, 77])
+def test_exact_ties_round_up_on_a_dyadic_transform(ctx, ell):
+    # N = 4, alpha = 2 gives the Walsh matrix (T T^T = 4 I): every product of
+    # the region kernel is then exact and A' - ell has denominator 16, so a
+    # share of the pixels sits exactly on a tie x + 1/2, which the paper's
+    # rounding floor(A' + 1/2) takes up; the device must agree bit for bit
+    T = o.rounded_klt(4, 0.9, 2.0)
+    assert np.array_equal(T @ T.T, 4 * np.eye(4, dtype=T.dtype))
+    tid = ctx.transform_id(4, 0.9, 2.0)
+    imgs = [ar1_image(64, 96, 0.9, seed=11), random_image(40, 136, seed=12)]
+    ties = 0
+    for r in (1, 2, 3, 6, 10, 16):
+        recs, out, per = run_plan(ctx, imgs, [tid] * 2, [r] * 2, [ell] * 2)
+        assert per[4] == 2
+        for img, rec, got in zip(imgs, recs, out):
+            ref = o.codec(img, 4, 0.9, 2.0, r, ell)
+            frac = ref["pre_round"] - np.floor(ref["pre_round"])
+            ties += int(np.count_nonzero(frac == 0.5))
+            assert np.array_equal(rec, ref["recon"]), (r, ell)
+            assert got["sse"] == ref["sse"]
+    assert ties > 100
