@@ -209,7 +209,8 @@ def uneven(ctx, steps: int) -> dict:
     out = {"images": len(specs), "pixels": pixels,
            "ms_per_launch_default": ms_default, "tiles_default": tiles_default,
            "ms_per_launch_autotuned": ms_tuned, "tiles_autotuned": plan.tiles,
-           "autotuned": {"wg_threads": t.wg_threads, "blocks_per_thread": t.blocks_per_thread},
+           "autotuned": {"wg_threads": t.wg_threads, "blocks_per_thread": t.blocks_per_thread,
+                         "schedule": "round_robin" if t.schedule else "contiguous"},
            "value": pixels / (ms_tuned / 1e3) / 1e6, "unit": "Mpixel/s",
            "hbm_frac": BYTES_PER_PIXEL * pixels / (ms_tuned / 1e3) / 1e9 / HBM_PEAK_GBS,
            "launches": plan.launches, "grid_wgs": plan.grid}

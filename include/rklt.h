@@ -115,7 +115,11 @@ typedef struct {
   int32_t wg_threads;        /* threads per workgroup: 64, 128 or 256            */
   int32_t blocks_per_thread; /* N = 8 path: N x N blocks per thread per tile     */
   int32_t grid_wgs;          /* persistent grid size in workgroups (0: auto)     */
-  int32_t reserved;
+  int32_t schedule;          /* batched matrix-core N = 8 kernel: 0 (default) one
+                                contiguous, cost-balanced run of tiles per
+                                workgroup; 1 tiles dealt round robin (workgroup
+                                w codes tiles w, w + grid, ...), so the grid
+                                sweeps the batch together; other values E_INVAL */
 } rklt_tuning;
 
 typedef struct rklt_ctx rklt_ctx;
@@ -288,8 +292,8 @@ rklt_status rklt_plan_run(rklt_plan* plan, rklt_result* d_res, void* stream);
 /* Tile-shape autotuning of the batched launch (a persistent grid over
  * uneven images; the tile shape and blocks per workgroup decide balance and
  * per-tile overhead): re-tiles the plan for each candidate tuning
- * (wg_threads in {128, 256} x blocks_per_thread in {1, 2, 4, 8}, grid at the
- * resident capacity), times `reps` runs of each on `stream` with HIP events
+ * (wg_threads in {128, 256} x blocks_per_thread in {1, 2, 4, 8} x schedule
+ * in {0, 1}, grid at the resident capacity), times `reps` runs of each on `stream` with HIP events
  * after one warm-up run, and keeps the fastest.  The runs code the plan's
  * images for real: dst and d_res hold a complete, valid result afterwards.
  * Synchronous (waits for the timing runs).  `chosen` (may be NULL) receives

@@ -33,6 +33,7 @@ struct PlanPart {
   int grid = 0;
   size_t off_imgs = 0, off_tile_img = 0, off_wg_tiles = 0;
   bool has_wg_tiles = false;
+  bool strided = false;  // matrix-core N = 8 kernel: tiles dealt round robin
   int mode = 0;  // panel kernel arithmetic (PanelMode)
 };
 
@@ -205,10 +206,11 @@ int image_tile_blocks(const DevImage& d, int base, int unit) {
   return tb;
 }
 
-rklt_status check_tuning(const rklt_tuning* tu, int* wg, int* bpt, int* grid) {
+rklt_status check_tuning(const rklt_tuning* tu, int* wg, int* bpt, int* grid, int* sched) {
   *wg = kDefaultWg;
   *bpt = kDefaultBpt;
   *grid = 0;
+  *sched = 0;
   if (!tu) return RKLT_OK;
   if (tu->wg_threads) {
     if (tu->wg_threads != 64 && tu->wg_threads != 128 && tu->wg_threads != 256)
@@ -222,7 +224,9 @@ rklt_status check_tuning(const rklt_tuning* tu, int* wg, int* bpt, int* grid) {
   }
   if (tu->grid_wgs < 0) return fail(RKLT_E_INVAL, "tuning: grid_wgs=%d is negative", tu->grid_wgs);
   *grid = tu->grid_wgs;
-  if (tu->reserved != 0) return fail(RKLT_E_INVAL, "tuning: reserved field is not 0");
+  if (tu->schedule != 0 && tu->schedule != 1)
+    return fail(RKLT_E_INVAL, "tuning: schedule=%d not in {0, 1}", tu->schedule);
+  *sched = tu->schedule;
   return RKLT_OK;
 }
 
@@ -714,8 +718,8 @@ rklt_status rklt_codec(rklt_ctx* ctx, const rklt_image* img, rklt_result* d_res,
                        void* stream) {
   clear_error();
   if (!ctx || !img || !d_res) return fail(RKLT_E_INVAL, "rklt_codec: NULL argument");
-  int wg, bpt, grid_req;
-  rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req);
+  int wg, bpt, grid_req, sched;
+  rklt_status st = check_tuning(tuning, &wg, &bpt, &grid_req, &sched);
   if (st) return st;
   if (!tuning) {
     // One image per launch: small tiles, so that even a 1-megapixel image
@@ -777,8 +781,8 @@ size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
 // Tile the images of one kernel class and append its work list to `img`
 // (the plan's host image of the device buffer).
-rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int N,
-                       PlanPart* q, std::vector<unsigned char>& img) {
+rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int wg, int bpt, int grid_req, int sched,
+                       int N, PlanPart* q, std::vector<unsigned char>& img) {
   const bool b8 = cls == 1 || cls == 2;
   // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds;
   // region kernel: tiles of 16 regions (4 per wave), small enough that the
@@ -824,7 +828,9 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
   for (size_t k = 0; k < imgs.size(); ++k)
     for (int t = 0; t < imgs[k].ntiles; ++t) tile_img[imgs[k].tile0 + t] = static_cast<int32_t>(k);
   std::vector<int32_t> wg_tiles;
-  q->has_wg_tiles = cls == 2 && q->grid > 0;
+  // round-robin tiles need no ranges; contiguous ones are cost-balanced
+  q->strided = cls == 2 && sched == 1;
+  q->has_wg_tiles = cls == 2 && q->grid > 0 && !q->strided;
   if (q->has_wg_tiles) {
     // Split the tiles into grid contiguous ranges of (nearly) equal estimated
     // cost: range w ends at the first tile where the running cost reaches
@@ -869,8 +875,8 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
 // the host image of its work list.
 rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   rklt_ctx* ctx = p->ctx;
-  int wg, bpt, grid_req;
-  rklt_status st = check_tuning(p->has_tuning ? &p->tuning : nullptr, &wg, &bpt, &grid_req);
+  int wg, bpt, grid_req, sched;
+  rklt_status st = check_tuning(p->has_tuning ? &p->tuning : nullptr, &wg, &bpt, &grid_req, &sched);
   if (st) return st;
   std::vector<DevImage> by_class[kClasses];  // indexed by kernel class
   std::vector<DevImage> all;
@@ -907,7 +913,7 @@ rklt_status build_plan(rklt_plan* p, const rklt_image* imgs, int32_t n) {
   p->h_image.clear();
   for (int c : {2, 4, 5, 6, 1, 3, 0}) {
     if (by_class[c].empty()) continue;
-    st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, N, &p->parts[p->nparts], p->h_image);
+    st = build_part(ctx, by_class[c], c, wg, bpt, grid_req, sched, N, &p->parts[p->nparts], p->h_image);
     if (st) return st;
     ++p->nparts;
   }
@@ -1071,34 +1077,33 @@ rklt_status rklt_plan_autotune(rklt_plan* p, rklt_result* d_res, int32_t reps, v
     if (ev[0]) (void)hipEventDestroy(ev[0]);
     return hip_fail("rklt_plan_autotune: hipEventCreate", e);
   }
-  // candidates: workgroup size and blocks per thread (tile size); the grid
-  // stays at the resident capacity
+  // candidates: workgroup size, blocks per thread (tile size) and the tile
+  // schedule of the matrix-core kernel; the grid stays at the resident
+  // capacity
   static const int kWg[] = {128, 256};
   static const int kBpt[] = {1, 2, 4, 8};
   rklt_tuning best{};
   float best_ms = -1.0f;
   rklt_status st_out = RKLT_OK;
-  for (int wg : kWg) {
-    for (int bpt : kBpt) {
-      const rklt_tuning t{wg, bpt, 0, 0};
-      if ((st_out = apply(t, true))) break;
-      if ((st_out = rklt_plan_run(p, d_res, stream))) break;  // warm-up
-      (void)hipEventRecord(ev[0], st);
-      for (int k = 0; k < reps && !st_out; ++k) st_out = rklt_plan_run(p, d_res, stream);
-      (void)hipEventRecord(ev[1], st);
-      if (st_out) break;
-      if ((e = hipEventSynchronize(ev[1])) != hipSuccess) {
-        st_out = hip_fail("rklt_plan_autotune: hipEventSynchronize", e);
-        break;
-      }
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
-      if (best_ms < 0.0f || ms < best_ms) {
-        best_ms = ms;
-        best = t;
-      }
-    }
+  for (int cand = 0; cand < 2 * 2 * 4 && !st_out; ++cand) {
+    const int sched = cand / 8, wg = kWg[(cand / 4) % 2], bpt = kBpt[cand % 4];
+    const rklt_tuning t{wg, bpt, 0, sched};
+    if ((st_out = apply(t, true))) break;
+    if ((st_out = rklt_plan_run(p, d_res, stream))) break;  // warm-up
+    (void)hipEventRecord(ev[0], st);
+    for (int k = 0; k < reps && !st_out; ++k) st_out = rklt_plan_run(p, d_res, stream);
+    (void)hipEventRecord(ev[1], st);
     if (st_out) break;
+    if ((e = hipEventSynchronize(ev[1])) != hipSuccess) {
+      st_out = hip_fail("rklt_plan_autotune: hipEventSynchronize", e);
+      break;
+    }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (best_ms < 0.0f || ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
   }
   (void)hipEventDestroy(ev[0]);
   (void)hipEventDestroy(ev[1]);
@@ -1134,6 +1139,7 @@ rklt_status rklt_plan_run(rklt_plan* p, rklt_result* d_res, void* stream) {
     a.res = d_res;
     a.total_tiles = static_cast<int32_t>(q.total_tiles);
     a.dump = p->dump ? 1 : 0;
+    a.strided = q.strided ? 1 : 0;
     const rklt_status st = q.cls == 2   ? launch_mfma8(a, q.grid, q.wg, stream)
                            : q.cls == 1 ? launch_block8(a, q.grid, q.wg, stream)
                            : q.cls >= 4 ? launch_mfma32(a, q.grid, q.cls - 4, stream)

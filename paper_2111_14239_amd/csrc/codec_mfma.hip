@@ -388,14 +388,22 @@ void rklt_mfma8_kernel(KArgs a) {
   int loaded = -1, loaded_r = -1;
   const ConstInt wg_tiles = (ConstInt)(a.wg_tiles);
   const ConstInt tile_img = (ConstInt)(a.tile_img);
-  // contiguous tile range of this workgroup: cost-balanced by the plan, or an
-  // equal share of the tiles
-  const int t_end = PLAN && a.wg_tiles ? wg_tiles[blockIdx.x + 1] : tile_end_of(a.total_tiles);
-  for (int t = PLAN && a.wg_tiles ? wg_tiles[blockIdx.x] : tile_begin(a.total_tiles); t < t_end;) {
+  // contiguous tile range of this workgroup (cost-balanced by the plan, or an
+  // equal share of the tiles), or, for a round-robin plan, tiles blockIdx.x,
+  // blockIdx.x + gridDim.x, ... each as a segment of its own (the whole grid
+  // then sweeps the batch together, which reads HBM in fewer, adjacent runs)
+  const bool strided = PLAN && a.strided;
+  const int t_end = strided              ? a.total_tiles
+                    : PLAN && a.wg_tiles ? wg_tiles[blockIdx.x + 1]
+                                         : tile_end_of(a.total_tiles);
+  for (int t = strided                ? static_cast<int>(blockIdx.x)
+               : PLAN && a.wg_tiles ? wg_tiles[blockIdx.x]
+                                    : tile_begin(a.total_tiles);
+       t < t_end;) {
     const int ii = PLAN ? __builtin_amdgcn_readfirstlane(tile_img[t]) : 0;
     const ConstImage im = PLAN ? (ConstImage)(a.imgs + ii) : (ConstImage)(&a.one);
     const int tile0 = im->tile0, ntiles = im->ntiles;
-    const int seg_end = tile0 + ntiles < t_end ? tile0 + ntiles : t_end;
+    const int seg_end = strided ? t + 1 : tile0 + ntiles < t_end ? tile0 + ntiles : t_end;
     const int tid = __builtin_amdgcn_readfirstlane(im->tid);
     const int r = __builtin_amdgcn_readfirstlane(im->r);
     const DevTransform* tf = a.tf + tid;
@@ -458,7 +466,7 @@ void rklt_mfma8_kernel(KArgs a) {
 #undef RKLT_SEG
     reduce_and_finish(sxx - 2u * sxy, red, a.res + im->slot, seg_end - t, ntiles,
                       static_cast<long long>(im->H) * im->W);
-    t = seg_end;
+    t = strided ? t + static_cast<int>(gridDim.x) : seg_end;
   }
 }
 

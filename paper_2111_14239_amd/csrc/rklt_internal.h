@@ -143,6 +143,7 @@ struct KArgs {
   rklt_result* res;          // one per image
   int32_t total_tiles;
   int32_t dump;               // write coefficient dumps
+  int32_t strided;            // matrix-core plans: workgroup w codes tiles w, w + grid, ...
   DevImage one;               // the image of the plain path
 };
 

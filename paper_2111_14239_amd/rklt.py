@@ -72,7 +72,7 @@ class DesignEntry(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("wg_threads", C.c_int32), ("blocks_per_thread", C.c_int32),
-                ("grid_wgs", C.c_int32), ("reserved", C.c_int32)]
+                ("grid_wgs", C.c_int32), ("schedule", C.c_int32)]
 
 
 def _load():
@@ -246,8 +246,8 @@ def _stream_handle(stream) -> int | None:
     return h or None
 
 
-def make_tuning(wg_threads=0, blocks_per_thread=0, grid_wgs=0):
-    return Tuning(int(wg_threads), int(blocks_per_thread), int(grid_wgs), 0)
+def make_tuning(wg_threads=0, blocks_per_thread=0, grid_wgs=0, schedule=0):
+    return Tuning(int(wg_threads), int(blocks_per_thread), int(grid_wgs), int(schedule))
 
 
 ROW_ALIGN = 128

@@ -219,7 +219,8 @@ UNEVEN = [(64, 72, 0.2, 2.0, 1, 11, 128), (8, 8, 0.95, 2.0, 64, 12, 128), (136, 
           (520, 64, 0.9, 3.0, 28, 16, 128), (16, 16, 0.3, 3.0, 50, 17, 128), (200, 200, 0.95, 2.0, 63, 18, 128)]
 
 
-@pytest.mark.parametrize("tuning", [None, (64, 1, 0), (128, 4, 7), (256, 2, 1)])
+@pytest.mark.parametrize("tuning", [None, (64, 1, 0), (128, 4, 7), (256, 2, 1),
+                                    (64, 1, 0, 1), (128, 4, 7, 1), (256, 2, 0, 1), (256, 8, 3, 1)])
 def test_batched_plan_matches_alone_and_oracle(ctx, tuning):
     tu = rklt.make_tuning(*tuning) if tuning else None
     xs, dsts, plan, res = _batch(ctx, UNEVEN, tu)
@@ -484,6 +485,7 @@ def test_autotune_keeps_results_and_rejects_bad_arguments(ctx):
     assert [(q["sse"], q["psnr_db"]) for q in rklt.read_results(res)] == before
     assert all(np.array_equal(d.cpu().numpy(), r) for d, r in zip(dsts, recon))
     assert (t.wg_threads, t.blocks_per_thread) in {(w, b) for w in (128, 256) for b in (1, 2, 4, 8)}
+    assert t.schedule in (0, 1) and t.grid_wgs == 0
     with pytest.raises(rklt.RkltError) as e:
         plan.autotune(int(res.data_ptr()), reps=0)
     assert e.value.status == rklt.E_INVAL
@@ -517,3 +519,13 @@ def test_precision_of_the_fp32_inverse(ctx, N):
         assert off / diff.size <= 2e-3
     print(f"\nN={N}: (r, share of pixels off by one, largest |x - tie| among them, |dPSNR| dB)",
           [(r, f"{s:.2e}", f"{t:.1e}", f"{p:.1e}") for r, s, t, p in stats])
+
+
+def test_tuning_is_validated(ctx):
+    x = torch.zeros((64, 64), dtype=torch.uint8, device="cuda")
+    d = rklt.image_desc(x, ctx.transform_id(8, 0.5, 2.0), 10, dst=torch.empty_like(x))
+    for bad in [(100, 0, 0, 0), (0, 17, 0, 0), (0, 0, -1, 0), (0, 0, 0, 2), (0, 0, 0, -1)]:
+        with pytest.raises(rklt.RkltError) as e:
+            ctx.plan([d], rklt.make_tuning(*bad))
+        assert e.value.status == rklt.E_INVAL and "tuning" in str(e.value)
+    ctx.plan([d], rklt.make_tuning(0, 0, 0, 1)).close()
