@@ -548,6 +548,10 @@ rklt_status rklt_ctx_add_transform(rklt_ctx* ctx, const rklt_transform* t, int32
         // one of its blocks (all four quadrants hold coefficients)
         dt.m32W[tt][lane] = static_cast<float>(t->s[c % N] * t->s[j % N]);
         dt.m32R[tt][lane] = static_cast<int16_t>(dt.rank[(c % N) * N + j % N]);
+        // Tb in fp16 (exact: |T_ij| <= 127) for the column stage; no lo part
+        dt.m32Ms[tt / 8][0][lane][tt % 8] =
+            static_cast<_Float16>(diag ? t->T[(c % N) * N + j % N] : 0);
+        dt.m32Ms[tt / 8][1][lane][tt % 8] = static_cast<_Float16>(0);
       }
     }
   }

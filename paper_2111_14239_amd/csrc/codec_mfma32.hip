@@ -8,8 +8,10 @@
 // independent).  Every stage is a 32 x 32 x 32 product:
 //   row stage      Y  = (A - 128) Tb^T + (128 - ell) sig   v_mfma_i32_32x32x32_i8
 //                  (the row sums of A - ell, from signed pixel bytes)
-//   column stage   B^T = Y^T Tb^T                two v_mfma_i32_32x32x32_i8
-//                  (Y = 256 hi + lo, hi and lo signed bytes)
+//   column stage   B^T = Y^T Tb^T             four v_mfma_f32_32x32x16_f16
+//                  (Y as two exact fp16 parts: |Y| < 2^15, so hi keeps 11
+//                  bits and lo < 16; Tb exact in fp16; every partial sum an
+//                  integer below 2^24, so B is exact in FP32)
 //   zonal + S      B_hat = (s_i s_j) B on the first r zig-zag positions, FP32
 //                  (quantised entries: B_hat = Q c, c = round(B / Q~) as in
 //                  Appendix A, on the same positions)
@@ -22,7 +24,7 @@
 //                  A' + ell + 2^-12 (the nudge sends exact ties up; it
 //                  differs from floor(x + 1/2) only within 2^-12 below a
 //                  tie, inside the FP32 inverse's own tie band)
-// so B = T (A - ell) T^T is exact int32 and the inverse is FP32 up to the
+// so B = T (A - ell) T^T is exact and the inverse is FP32 up to the
 // dropped lo lo terms (relative 2^-22).
 //
 // Layouts.  With h = lane / 32 and c = lane % 32, accumulator register t of
@@ -89,14 +91,6 @@ __device__ __forceinline__ void split_parts(const float* x, v8f16& hi, v8f16& lo
   wl[3] = l3;
   hi = __builtin_bit_cast(v8f16, wh);
   lo = __builtin_bit_cast(v8f16, wl);
-}
-
-// Byte b of a, c, e, g (in that order) as one word: two v_perm_b32 put the
-// bytes of (a, c) and (e, g) in place, a third merges them.
-__device__ __forceinline__ uint32_t gather_byte(uint32_t a, uint32_t c, uint32_t e, uint32_t g, uint32_t b) {
-  const uint32_t lo2 = __builtin_amdgcn_perm(c, a, 0x0c0c0400u | (b * 0x0101u));          // [a.b, c.b, 0, 0]
-  const uint32_t hi2 = __builtin_amdgcn_perm(g, e, 0x04000c0cu | (b * 0x01010000u));      // [0, 0, e.b, g.b]
-  return __builtin_amdgcn_perm(hi2, lo2, 0x07060100u);
 }
 
 // Waves per workgroup; they take consecutive regions.
@@ -199,8 +193,8 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       for (int k = 0; k < 2; ++k) {
         Gh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][0][lane][0]);
         Gl[k] = *reinterpret_cast<const v8f16*>(&tf->m32Gs[k][1][lane][0]);
+        Mh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Ms[k][0][lane][0]);
         if (FLT) {
-          Mh[k] = *reinterpret_cast<const v8f16*>(&tf->m32Ms[k][0][lane][0]);
           Ml[k] = *reinterpret_cast<const v8f16*>(&tf->m32Ms[k][1][lane][0]);
         }
       }
@@ -210,8 +204,8 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
     const int N = __builtin_amdgcn_readfirstlane(as_constant(tf)->N);
     const int D = __builtin_amdgcn_readfirstlane(im->D);
     const int ell = __builtin_amdgcn_readfirstlane(im->ell);
-    // row-sum correction of this lane's column, plus the 128 of the byte split
-    const int lift128 = (128 - ell) * S + 128;
+    // row-sum correction of this lane's column (zero at ell = 128)
+    const int lift = (128 - ell) * S;
     const float out_bias = static_cast<float>(ell) + 0x1p-12f;
     const float fell = static_cast<float>(ell);
     uint32_t keep = 0;
@@ -306,26 +300,27 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
         const v4i32 X = {static_cast<int>(x[0] ^ 0x80808080u), static_cast<int>(x[1] ^ 0x80808080u),
                          static_cast<int>(x[2] ^ 0x80808080u), static_cast<int>(x[3] ^ 0x80808080u)};
         v16i32 Y = __builtin_amdgcn_mfma_i32_32x32x32_i8(X, Tw, zi, 0, 0, 0);
-        // column stage on the signed bytes of Y = 256 hi + lo: with
-        // Y' = Y + 128 (plus the level-shift correction), lo is byte 0 of Y'
-        // xor 0x80 and hi is byte 1 of Y'
-        v4i32 lo, hi;
+        // column stage on the two fp16 parts of Y (|Y| < 2^15: hi keeps 11
+        // bits, lo < 16 is exact) against Tb in fp16: every product and
+        // partial sum is an integer below 2^24, so B comes out exact in FP32
+        if (ell != 128) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) Y[t] += lift128;
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const uint32_t a = Y[4 * w], c2 = Y[4 * w + 1], e = Y[4 * w + 2], g2 = Y[4 * w + 3];
-          lo[w] = static_cast<int>(gather_byte(a, c2, e, g2, 0) ^ 0x80808080u);
-          hi[w] = static_cast<int>(gather_byte(a, c2, e, g2, 1));
+          for (int t = 0; t < 16; ++t) Y[t] += lift;
         }
-        const v16i32 Bl = __builtin_amdgcn_mfma_i32_32x32x32_i8(lo, Tw, zi, 0, 0, 0);
-        const v16i32 Bh = __builtin_amdgcn_mfma_i32_32x32x32_i8(hi, Tw, zi, 0, 0, 0);
+        float Yr[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Yr[t] = static_cast<float>(Y[t]);
+        v16f32 Bf = zf;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          v8f16 ah, al;
+          split_parts(&Yr[8 * k], ah, al);
+          Bf = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, Mh[k], Bf, 0, 0, 0);
+          Bf = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Mh[k], Bf, 0, 0, 0);
+        }
         // register t: B[c][kap(t, h)], scaled and masked
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const int B = Bh[t] * 256 + Bl[t];
-          Bs[t] = QUANT ? quantise(B, WM[t], QS[t]) : static_cast<float>(B) * WM[t];
-        }
+        for (int t = 0; t < 16; ++t) Bs[t] = QUANT ? quantise(Bf[t], WM[t], QS[t]) : Bf[t] * WM[t];
       }
       // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
       v16f32 Z = zf, O = zf;

@@ -58,12 +58,16 @@ __host__ __device__ constexpr int zz_rank(int n, int i, int j) {
 // floor(t) + [t - floor(t) >= 1/2]; returns the dequantised coefficient of
 // T_hat A T_hat^T, Q c.  Contraction is off so that t is rounded once and
 // the decision is taken on that FP32 value, not on an FMA's exact product.
-__device__ __forceinline__ float quantise(int B, float qinv, float qstep) {
+// B is an integer held exactly in FP32 (|B| < 2^24).
+__device__ __forceinline__ float quantise(float B, float qinv, float qstep) {
 #pragma clang fp contract(off)
-  const float t = static_cast<float>(B) * qinv;
+  const float t = B * qinv;
   const float f = floorf(t);
   const float c = f + (t - f >= 0.5f ? 1.0f : 0.0f);
   return c * qstep;
+}
+__device__ __forceinline__ float quantise(int B, float qinv, float qstep) {
+  return quantise(static_cast<float>(B), qinv, qstep);
 }
 
 __device__ __forceinline__ int dot2(int a, int b, int acc) {

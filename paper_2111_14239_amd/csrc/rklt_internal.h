@@ -97,7 +97,7 @@ struct alignas(256) DevTransform {
   // Gb likewise for T_hat^-1.  With h = lane / 32, c = lane % 32 and
   // kap(t, h) = 8 (t / 4) + 4 h + t % 4 (the row of accumulator register t):
   //   m32T[lane][w]  int8x4 words, byte e of word w = Tb[c][kap(4w + e, h)]:
-  //                  B operand of both int8 stages (row and column);
+  //                  B operand of the int8 row stage;
   //   m32W[t][lane]  s_i s_j of region coefficient (c, kap(t, h)), which is
   //                  coefficient (c % N, kap(t, h) % N) of one of the region's
   //                  blocks; m32R[t][lane] its zig-zag rank.
@@ -109,7 +109,8 @@ struct alignas(256) DevTransform {
   // m32_sig: the largest |sig_j| (bounds the corrected row sums).
   //   m32Ms[k][p][lane][e]  float transforms: Mb[c][kap(8k + e, h)] (M on
   //                  the block diagonal) as two fp16 parts: B operands of the
-  //                  row and column stages.
+  //                  row and column stages; integer transforms: Tb in fp16
+  //                  (exact, p = 1 zero), the B operand of the column stage.
   int32_t m32_ok, m32_sig, m32_pad[2];
   int32_t m32T[64][4];
   int32_t m32S[64];
