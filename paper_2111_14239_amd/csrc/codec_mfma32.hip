@@ -152,18 +152,22 @@ __device__ __forceinline__ void load_segment(__amdgpu_buffer_rsrc_t rs, const Re
 // transforms (the comparison arms): the row and column stages run on fp16
 // products of (pixel - ell), exact in fp16, and two-part M, with FP32 sums.
 template <bool PLAN, int MODE>
-__global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
+__global__ __launch_bounds__(64 * kM32Waves) __attribute__((amdgpu_waves_per_eu(4))) void rklt_mfma32_kernel(KArgs a) {
   __shared__ unsigned long long red[kM32Waves];
   const int lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
   int loaded = -1, loaded_r = -1;
   v4i32 Tw = {0, 0, 0, 0};
   int S = 0;  // sig of this lane's region column
-  float WM[16], QS[16];  // scale (or 1 / Q~) of each kept coefficient, 0 otherwise; Q
+  float WM[16];  // scale of each kept coefficient, 0 otherwise
   v8f16 Gh[2] = {}, Gl[2] = {}, Mh[2] = {}, Ml[2] = {};
   constexpr bool QUANT = MODE == 1, FLT = MODE == 2;
+  // quantiser: 1 / Q~ of each kept coefficient (0 otherwise) and Q, per lane
+  // in LDS (float4 k of lane l at [wave][k][l]: registers 4k .. 4k + 3, 1 / Q~
+  // for k < 4, Q for k >= 4) rather than in 32 more VGPRs
+  __shared__ float4 qtab[QUANT ? kM32Waves : 1][8][64];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) WM[t] = QS[t] = 0.0f;
+  for (int t = 0; t < 16; ++t) WM[t] = 0.0f;
   const v16i32 zi = {};
   const v16f32 zf = {};
   const ConstInt tile_img = (ConstInt)(a.tile_img);
@@ -180,10 +184,17 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
       if (QUANT) {
         const int Nt = tf->N;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const int idx = (c % Nt) * Nt + kap(t, h) % Nt;
-          WM[t] = tf->m32R[t][lane] < r ? tf->qinv[idx] : 0.0f;
-          QS[t] = tf->qstep[idx];
+        for (int k = 0; k < 4; ++k) {
+          float wq[4], qs[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int t = 4 * k + v;
+            const int idx = (c % Nt) * Nt + kap(t, h) % Nt;
+            wq[v] = tf->m32R[t][lane] < r ? tf->qinv[idx] : 0.0f;
+            qs[v] = tf->qstep[idx];
+          }
+          qtab[wave][k][lane] = make_float4(wq[0], wq[1], wq[2], wq[3]);
+          qtab[wave][4 + k][lane] = make_float4(qs[0], qs[1], qs[2], qs[3]);
         }
       } else {
 #pragma unroll
@@ -319,8 +330,19 @@ __global__ __launch_bounds__(64 * kM32Waves) void rklt_mfma32_kernel(KArgs a) {
           Bf = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, Mh[k], Bf, 0, 0, 0);
         }
         // register t: B[c][kap(t, h)], scaled and masked
+        if constexpr (QUANT) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) Bs[t] = QUANT ? quantise(Bf[t], WM[t], QS[t]) : Bf[t] * WM[t];
+          for (int k = 0; k < 4; ++k) {
+            const float4 wq = qtab[wave][k][lane], qs = qtab[wave][4 + k][lane];
+            Bs[4 * k + 0] = quantise(Bf[4 * k + 0], wq.x, qs.x);
+            Bs[4 * k + 1] = quantise(Bf[4 * k + 1], wq.y, qs.y);
+            Bs[4 * k + 2] = quantise(Bf[4 * k + 2], wq.z, qs.z);
+            Bs[4 * k + 3] = quantise(Bf[4 * k + 3], wq.w, qs.w);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 16; ++t) Bs[t] = Bf[t] * WM[t];
+        }
       }
       // inverse: Z = B_hat Gb^T, then A'^T = Z^T Gb^T
       v16f32 Z = zf, O = zf;
