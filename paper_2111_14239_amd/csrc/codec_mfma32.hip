@@ -63,6 +63,7 @@ typedef float v16f32 __attribute__((ext_vector_type(16)));
 typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
 typedef _Float16 v8f16 __attribute__((ext_vector_type(8)));
+typedef _Float16 v2f16 __attribute__((ext_vector_type(2)));
 
 // Eight FP32 values as two fp16 parts: hi = x rounded toward zero, lo = the
 // remainder x - hi (exact inside a mixed-precision FMA) rounded to fp16;
@@ -218,7 +219,8 @@ __global__ __launch_bounds__(64 * kM32Waves) __attribute__((amdgpu_waves_per_eu(
     // row-sum correction of this lane's column (zero at ell = 128)
     const int lift = (128 - ell) * S;
     const float out_bias = static_cast<float>(ell) + 0x1p-12f;
-    const float fell = static_cast<float>(ell);
+    const _Float16 e1024 = static_cast<_Float16>(1024 + ell);  // exact
+    const v2f16 ell1024 = {e1024, e1024};
     uint32_t keep = 0;
 #pragma unroll
     for (int t = 0; t < 16; ++t)
@@ -275,7 +277,9 @@ __global__ __launch_bounds__(64 * kM32Waves) __attribute__((amdgpu_waves_per_eu(
       float Bs[16];
       if constexpr (FLT) {
         // row stage: K chunk k of lane l is pixel words x[2k], x[2k + 1]
-        // (columns kap(8k .. 8k + 7, h)), as fp16 pixel - ell
+        // (columns kap(8k .. 8k + 7, h)), as fp16 pixel - ell: a byte b
+        // under the high byte 0x64 is the fp16 1024 + b, and one packed fp16
+        // subtraction of 1024 + ell gives b - ell exactly, two pixels at once
         v16f32 Yf = zf;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -283,9 +287,9 @@ __global__ __launch_bounds__(64 * kM32Waves) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
           for (int p = 0; p < 4; ++p) {
             const uint32_t xw = x[2 * k + p / 2];
-            const float v0 = static_cast<float>((xw >> (16 * (p % 2))) & 0xffu) - fell;
-            const float v1 = static_cast<float>((xw >> (16 * (p % 2) + 8)) & 0xffu) - fell;
-            w[p] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(v0, v1));  // exact
+            // [byte 2(p % 2), 0x64, byte 2(p % 2) + 1, 0x64]
+            const uint32_t b1024 = __builtin_amdgcn_perm(0x64646464u, xw, p % 2 ? 0x04030402u : 0x04010400u);
+            w[p] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(v2f16, b1024) - ell1024);
           }
           const v8f16 A = __builtin_bit_cast(v8f16, w);
           Yf = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, Mh[k], Yf, 0, 0, 0);
