@@ -456,9 +456,20 @@ def test_uneven_batch_full_size(ctx):
     assert [p["sse"] for p in plain] == [q["sse"] for q in got]
     # autotuned tiling: same results
     t = plan.autotune(int(res.data_ptr()), reps=1)
-    assert t.wg_threads in (128, 256) and t.blocks_per_thread in (1, 2, 4, 8)
+    assert t.wg_threads in (128, 256) and t.blocks_per_thread in (1, 2, 4, 8) and t.schedule in (0, 1)
     torch.cuda.synchronize()
     assert [q["sse"] for q in rklt.read_results(res)] == [p["sse"] for p in plain]
+    # both tile schedules explicitly: the same reconstructions and results
+    for sched in (0, 1):
+        d2 = [torch.zeros_like(x) for x in srcs[:64]]
+        plan2 = ctx.plan([rklt.image_desc(x, tt, s.r, dst=d) for x, d, tt, s in zip(srcs, d2 + dsts[64:], tids, specs)],
+                         rklt.make_tuning(256, 8, 0, sched))
+        res2 = rklt.new_results(len(specs))
+        plan2.run(int(res2.data_ptr()))
+        torch.cuda.synchronize()
+        assert [q["sse"] for q in rklt.read_results(res2)] == [p["sse"] for p in plain], sched
+        assert all(torch.equal(a, b) for a, b in zip(d2, dsts[:64])), sched
+        plan2.close()
     # sampled blocks of a few images against the oracle
     rng = np.random.default_rng(7)
     for k in rng.choice(len(specs), size=4, replace=False):
