@@ -35,7 +35,7 @@
 // accumulator registers as they are: K element e of lane l is index
 // kap(e, h) (for fp16 operands, chunk k of a product takes registers
 // 8k .. 8k + 7), and the tables m32T, m32Gs, m32Ms of the transform record
-// hold Tb, Gb and Mb in that order.  Lane l holds row c of the region at the
+// hold Tb (int8), Gb and Mb (for an integer T: Tb in fp16) in that order.  Lane l holds row c of the region at the
 // pixel columns kap(0..15, h) (the words at columns 8q + 4h), and the last
 // product returns exactly those pixels of the reconstruction to it, so the
 // squared error needs no exchange.  Memory is accessed 16 contiguous bytes
