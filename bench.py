@@ -410,7 +410,7 @@ def main():
                     help="skip the single-image latency and the N in {4, 16, 32} batches")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the codec shards by whole images with no exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
 
