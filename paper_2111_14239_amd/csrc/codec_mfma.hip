@@ -391,7 +391,8 @@ void rklt_mfma8_kernel(KArgs a) {
   // contiguous tile range of this workgroup (cost-balanced by the plan, or an
   // equal share of the tiles), or, for a round-robin plan, tiles blockIdx.x,
   // blockIdx.x + gridDim.x, ... each as a segment of its own (the whole grid
-  // then sweeps the batch together, which reads HBM in fewer, adjacent runs)
+  // then sweeps the batch together; which schedule is faster depends on the
+  // batch, and the autotuner tries both)
   const bool strided = PLAN && a.strided;
   const int t_end = strided              ? a.total_tiles
                     : PLAN && a.wg_tiles ? wg_tiles[blockIdx.x + 1]
