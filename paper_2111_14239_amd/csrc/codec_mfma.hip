@@ -39,12 +39,14 @@ namespace rklt {
 namespace {
 
 // Occupancy target (waves per SIMD the register allocation must allow) and
-// depth of the pixel prefetch ring (steps in flight per wave, 2 or 3).
+// depth of the pixel prefetch ring (steps in flight per wave, 2 or 3).  Four
+// waves with two steps each in flight (128 VGPRs) beat three waves with
+// three steps each by 3% back to back.
 #ifndef RKLT_MFMA_WAVES_PER_EU
-#define RKLT_MFMA_WAVES_PER_EU 3
+#define RKLT_MFMA_WAVES_PER_EU 4
 #endif
 #ifndef RKLT_MFMA_RING
-#define RKLT_MFMA_RING 3
+#define RKLT_MFMA_RING 2
 #endif
 // Cache-policy bits of the pixel loads and reconstruction stores.  The
 // reconstruction is written once and not read again by the kernel:
