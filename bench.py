@@ -532,7 +532,7 @@ def main():
                                                  "matrix_core_region", "matrix_core_region_quantised",
                                                  "matrix_core_region_float"),
                                                 plan.images_per_class)),
-            "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 4,
+            "wg_threads": args.wg or 256, "blocks_per_thread": args.bpt or 1,
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

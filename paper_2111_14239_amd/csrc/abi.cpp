@@ -73,7 +73,7 @@ namespace {
 thread_local char g_error[512] = "";
 
 constexpr int kDefaultWg = 256;
-constexpr int kDefaultBpt = 4;
+constexpr int kDefaultBpt = 1;
 
 // Kernel class of an image (see kClasses).  Coefficient dumps are written by
 // the register and panel kernels.
