@@ -789,10 +789,12 @@ rklt_status build_part(rklt_ctx* ctx, std::vector<DevImage>& imgs, int cls, int 
                        int N, PlanPart* q, std::vector<unsigned char>& img) {
   const bool b8 = cls == 1 || cls == 2;
   // panel kernel: tiles of 64 panels (16 per wave), grown in whole rounds;
-  // region kernel: tiles of 16 regions (4 per wave), small enough that the
-  // resident grid's equal shares of tiles balance
+  // region kernel: tiles of 64 regions (16 per wave); smaller tiles spend
+  // more on per-tile set-up and result atomics (16 regions: 5-10% slower),
+  // larger ones leave the resident grid's equal shares uneven on batches of
+  // ~2800 tiles (128: 15% slower there)
   const int PB = panel_blocks(N);
-  const int base = cls == 2 ? (wg / 2) * bpt : cls == 1 ? wg * bpt : cls >= 4 ? 16 : 64 * PB;
+  const int base = cls == 2 ? (wg / 2) * bpt : cls == 1 ? wg * bpt : cls >= 4 ? 64 : 64 * PB;
   const int unit = cls == 2 ? wg / 2 : cls == 1 ? wg : cls >= 4 ? 4 : 4 * PB;
   q->mode = cls == 3 ? kPanelFloat : kPanelInt8;
   int64_t total = 0;
